@@ -1,0 +1,25 @@
+"""CPU oracle for Smith-Waterman/Gotoh database search scores.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+calls this package; only the test suite, the smoke check and the benchmark's
+CPU-baseline leg use it.  It shares no code, tables or helpers with the GPU
+path.
+
+What it computes (paper section 2.2: Smith-Waterman local alignment by
+dynamic programming; section 4.1: BLOSUM62 with gap penalties 10(2)): for a
+query a and each database sequence b, the best local alignment score
+
+    SW(a, b) = max(0, max over chains of matched pairs
+                         sum S(a_i, b_j) - sum of gap costs),
+    gap cost w(k) = o + (k - 1) * e  for a gap of k >= 1 residues.
+
+Three implementations, each written from that definition:
+  * sw_bruteforce  - enumerates every chain (tiny inputs only);
+  * sw_gotoh       - Gotoh's H/E/F recurrence in plain Python;
+  * cpu.search     - the same recurrence in plain scalar C (oracle/sw_oracle.c),
+                     threaded over database sequences; the timed CPU baseline
+                     and the parity source for full-size workloads.
+"""
+from .sw_ref import gap_cost, sw_bruteforce, sw_bruteforce_table, sw_gotoh
+
+__all__ = ["gap_cost", "sw_bruteforce", "sw_bruteforce_table", "sw_gotoh"]

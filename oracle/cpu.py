@@ -1,0 +1,77 @@
+"""ctypes wrapper of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB) or (
+                os.path.getmtime(_build.LIB) < os.path.getmtime(_build.SRC)):
+            _build.build()
+        lib = ctypes.CDLL(_build.LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        lib.swo_score.restype = I64
+        lib.swo_score.argtypes = [P, I64, P, I64, P, ctypes.c_int32, I64, I64]
+        lib.swo_search.restype = ctypes.c_int
+        lib.swo_search.argtypes = [P, I64, P, P, P, I64, P, ctypes.c_int32, I64, I64, P,
+                                   ctypes.c_int32]
+        _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    env = os.environ.get("OMP_NUM_THREADS")
+    n = os.cpu_count() or 1
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def score(a, b, S, gap_open: int, gap_extend: int) -> int:
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    k = S.shape[0]
+    r = _load().swo_score(_ptr(a), len(a), _ptr(b), len(b), _ptr(S), k, gap_open, gap_extend)
+    if r < 0:
+        raise MemoryError("oracle allocation failed")
+    return int(r)
+
+
+def search(query, residues, offsets, S, gap_open: int, gap_extend: int,
+           ids: Optional[np.ndarray] = None, threads: Optional[int] = None) -> np.ndarray:
+    """Scores of `query` against every database sequence (or the subset `ids`)."""
+    q = np.ascontiguousarray(query, dtype=np.uint8)
+    res = np.ascontiguousarray(residues, dtype=np.uint8)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n_items = len(ids)
+    else:
+        n_items = len(offs) - 1
+    out = np.zeros(n_items, dtype=np.int64)
+    if n_items == 0:
+        return out
+    rc = _load().swo_search(_ptr(q), len(q), _ptr(res), _ptr(offs),
+                            _ptr(ids) if ids is not None else None, n_items,
+                            _ptr(S), S.shape[0], gap_open, gap_extend, _ptr(out),
+                            threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle search failed")
+    return out

@@ -1,0 +1,108 @@
+"""Pure-Python oracle implementations (test infrastructure only).
+
+Both functions follow the Smith-Waterman local alignment score of paper
+section 2.2, with the affine gap penalty "10(2)" of section 4.1 read as
+w(k) = gap_open + (k - 1) * gap_extend (gap_open is the cost of a one-residue
+gap).  Sequences are integer codes indexing the substitution matrix S, with
+S[x][y] the score of query residue x against database residue y.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from typing import Iterable, List, Sequence, Tuple
+
+import numpy as np
+
+
+def gap_cost(k: int, gap_open: int, gap_extend: int) -> int:
+    """Cost of a run of k unmatched residues in one sequence; w(0) = 0."""
+    if k == 0:
+        return 0
+    return gap_open + (k - 1) * gap_extend
+
+
+def _chains(m: int, n: int):
+    """Every chain (i_1 < ... < i_r, j_1 < ... < j_r), r >= 1."""
+    for r in range(1, min(m, n) + 1):
+        for I in itertools.combinations(range(m), r):
+            for J in itertools.combinations(range(n), r):
+                yield I, J
+
+
+def sw_bruteforce(a: Sequence[int], b: Sequence[int], S, gap_open: int,
+                  gap_extend: int) -> int:
+    """Definition of the local alignment score, by enumeration of all chains.
+
+    A local alignment matches residue pairs (i_t, j_t) strictly increasing in
+    both sequences; between consecutive matched pairs the skipped residues of
+    each sequence form one gap.  Its score is the sum of the matched pairs'
+    substitution scores minus the gaps' costs; the empty alignment scores 0.
+    Exponential: for tiny inputs only.
+    """
+    best = 0
+    for I, J in _chains(len(a), len(b)):
+        s = sum(int(S[a[i]][b[j]]) for i, j in zip(I, J))
+        for t in range(len(I) - 1):
+            s -= gap_cost(I[t + 1] - I[t] - 1, gap_open, gap_extend)
+            s -= gap_cost(J[t + 1] - J[t] - 1, gap_open, gap_extend)
+        best = max(best, s)
+    return best
+
+
+def sw_bruteforce_table(a: Sequence[int], b: Sequence[int], S,
+                        gaps: Iterable[Tuple[int, int]]) -> List[int]:
+    """sw_bruteforce for several (gap_open, gap_extend) pairs at once.
+
+    Each chain is summarised by (substitution sum, number of gaps, residues
+    beyond the first in every gap), so that its score under (o, e) is
+    sub - n_gaps * o - n_ext * e; the maximum is then taken per (o, e).
+    """
+    sub, ngap, next_ = [], [], []
+    for I, J in _chains(len(a), len(b)):
+        sub.append(sum(int(S[a[i]][b[j]]) for i, j in zip(I, J)))
+        g = x = 0
+        for t in range(len(I) - 1):
+            for k in (I[t + 1] - I[t] - 1, J[t + 1] - J[t] - 1):
+                if k > 0:
+                    g += 1
+                    x += k - 1
+        ngap.append(g)
+        next_.append(x)
+    sub = np.array(sub, dtype=np.int64)
+    ngap = np.array(ngap, dtype=np.int64)
+    next_ = np.array(next_, dtype=np.int64)
+    out = []
+    for o, e in gaps:
+        if len(sub) == 0:
+            out.append(0)
+        else:
+            out.append(int(max(0, (sub - ngap * o - next_ * e).max())))
+    return out
+
+
+def sw_gotoh(a: Sequence[int], b: Sequence[int], S, gap_open: int,
+             gap_extend: int) -> int:
+    """Gotoh's three-matrix recurrence for the same score, in plain Python.
+
+    With rows i = 1..m over the query and columns j = 1..n over the database
+    sequence:
+        E(i,j) = max(E(i,j-1) - e, H(i,j-1) - o)      gap along the database
+        F(i,j) = max(F(i-1,j) - e, H(i-1,j) - o)      gap along the query
+        H(i,j) = max(0, H(i-1,j-1) + S(a_i, b_j), E(i,j), F(i,j))
+    with H = 0 and E = F = -infinity on the borders; the score is max H.
+    """
+    m, n = len(a), len(b)
+    NEG = -math.inf
+    H = [[0] * (n + 1) for _ in range(m + 1)]
+    E = [[NEG] * (n + 1) for _ in range(m + 1)]
+    F = [[NEG] * (n + 1) for _ in range(m + 1)]
+    best = 0
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            E[i][j] = max(E[i][j - 1] - gap_extend, H[i][j - 1] - gap_open)
+            F[i][j] = max(F[i - 1][j] - gap_extend, H[i - 1][j] - gap_open)
+            H[i][j] = max(0, H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]),
+                          E[i][j], F[i][j])
+            best = max(best, H[i][j])
+    return int(best)

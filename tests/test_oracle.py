@@ -1,0 +1,242 @@
+"""Pins of the CPU oracle against what the mathematics fixes.
+
+The paper prints no scores, so the oracle is pinned by: brute-force
+enumeration of the definition on tiny inputs (exhaustive over gap penalties,
+random non-symmetric matrices), textbook reductions (linear-gap SW, per-diagonal
+Kadane, LCS), closed forms under BLOSUM62, hand-derived cases in
+tests/golden/hand_cases.txt, and invariants.  Each is chosen so that a dropped
+term, a wrong sign or index, a transposed operand or a different gap
+convention in the oracle fails at least one test.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.cpu as ocpu
+import swinputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+B62 = swinputs.blosum62()
+GAPS_SMALL = [(o, e) for o in range(0, 7) for e in range(0, o + 1)]
+
+
+# ----------------------------------------------------------------- tiny inputs
+def _tiny_cases(seed, count, alpha_max=4, len_max=6):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        k = int(rng.integers(2, alpha_max + 1))
+        m = int(rng.integers(0, len_max + 1))
+        n = int(rng.integers(0, len_max + 1))
+        a = rng.integers(0, k, m).astype(np.uint8)
+        b = rng.integers(0, k, n).astype(np.uint8)
+        # non-symmetric matrix with mixed signs, sometimes all-negative rows
+        S = rng.integers(-6, 7, size=(k, k)).astype(np.int8)
+        if rng.random() < 0.2:
+            S[int(rng.integers(0, k))] = -rng.integers(1, 5, size=k)
+        yield a, b, S
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_recurrence_equals_definition_bruteforce(seed):
+    """Gotoh (Python and C) == chain enumeration, for every 0 <= e <= o <= 6."""
+    for a, b, S in _tiny_cases(seed, 25):
+        want = oracle.sw_bruteforce_table(a, b, S, GAPS_SMALL)
+        for (o, e), w in zip(GAPS_SMALL, want):
+            assert oracle.sw_gotoh(a, b, S, o, e) == w, (a, b, S, o, e)
+            assert ocpu.score(a, b, S, o, e) == w, (a, b, S, o, e)
+
+
+def test_bruteforce_table_matches_direct_enumeration():
+    for a, b, S in _tiny_cases(99, 20, len_max=5):
+        tab = oracle.sw_bruteforce_table(a, b, S, GAPS_SMALL)
+        for (o, e), w in zip(GAPS_SMALL, tab):
+            assert oracle.sw_bruteforce(a, b, S, o, e) == w
+
+
+def test_other_gap_convention_by_shifted_open():
+    """w(k) = o + k e (open counted on top of every residue) is the oracle with open o + e."""
+    rng = np.random.default_rng(7)
+    for a, b, S in _tiny_cases(8, 30):
+        o = int(rng.integers(0, 6)); e = int(rng.integers(0, 4))
+        best = 0
+        for I, J in oracle.sw_ref._chains(len(a), len(b)):
+            s = sum(int(S[a[i]][b[j]]) for i, j in zip(I, J))
+            for t in range(len(I) - 1):
+                for k in (I[t + 1] - I[t] - 1, J[t + 1] - J[t] - 1):
+                    if k:
+                        s -= o + k * e
+            best = max(best, s)
+        assert ocpu.score(a, b, S, o + e, e) == best
+
+
+def test_hand_cases():
+    n = 0
+    with open(os.path.join(HERE, "golden", "hand_cases.txt")) as f:
+        for ln in f:
+            if not ln.strip() or ln.startswith("#"):
+                continue
+            q, t, o, e, want = ln.split()
+            a, b = swinputs.encode(q), swinputs.encode(t)
+            assert oracle.sw_gotoh(a, b, B62, int(o), int(e)) == int(want), ln
+            assert ocpu.score(a, b, B62, int(o), int(e)) == int(want), ln
+            n += 1
+    assert n >= 6
+
+
+# ------------------------------------------------------- textbook reductions
+def _linear_sw(a, b, S, g):
+    """Single-matrix Smith-Waterman with linear gap cost g per residue."""
+    m, n = len(a), len(b)
+    H = np.zeros((m + 1, n + 1), dtype=np.int64)
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            H[i, j] = max(0, H[i - 1, j - 1] + int(S[a[i - 1]][b[j - 1]]),
+                          H[i - 1, j] - g, H[i, j - 1] - g)
+    return int(H.max())
+
+
+def _kadane_diagonals(a, b, S):
+    """Best ungapped local alignment: max subarray along every diagonal."""
+    best = 0
+    m, n = len(a), len(b)
+    for d in range(-(m - 1), n):
+        run = 0
+        for i in range(m):
+            j = i + d
+            if 0 <= j < n:
+                run = max(0, run + int(S[a[i]][b[j]]))
+                best = max(best, run)
+    return best
+
+
+def _lcs(a, b):
+    m, n = len(a), len(b)
+    L = np.zeros((m + 1, n + 1), dtype=np.int64)
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            L[i, j] = L[i - 1, j - 1] + 1 if a[i - 1] == b[j - 1] else max(L[i - 1, j], L[i, j - 1])
+    return int(L[m, n])
+
+
+def test_equal_open_extend_is_linear_gap_sw():
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        m, n = rng.integers(0, 40, 2)
+        a = rng.integers(0, 20, m).astype(np.uint8)
+        b = rng.integers(0, 20, n).astype(np.uint8)
+        g = int(rng.integers(0, 9))
+        assert ocpu.score(a, b, B62, g, g) == _linear_sw(a, b, B62, g)
+
+
+def test_prohibitive_gaps_is_per_diagonal_kadane():
+    rng = np.random.default_rng(12)
+    for _ in range(60):
+        m, n = rng.integers(0, 50, 2)
+        a = rng.integers(0, 24, m).astype(np.uint8)
+        b = rng.integers(0, 24, n).astype(np.uint8)
+        big = 11 * 60 + 1
+        assert ocpu.score(a, b, B62, big, big) == _kadane_diagonals(a, b, B62)
+        assert oracle.sw_gotoh(a, b, B62, big, 0) == _kadane_diagonals(a, b, B62)
+
+
+def test_free_gaps_unit_match_is_lcs():
+    rng = np.random.default_rng(13)
+    k = 4
+    S = -np.ones((k, k), dtype=np.int8) + 2 * np.eye(k, dtype=np.int8)
+    for _ in range(60):
+        m, n = rng.integers(0, 40, 2)
+        a = rng.integers(0, k, m).astype(np.uint8)
+        b = rng.integers(0, k, n).astype(np.uint8)
+        assert ocpu.score(a, b, S, 0, 0) == _lcs(a, b)
+
+
+# ------------------------------------------------ closed forms under BLOSUM62
+def test_blosum62_table_shape():
+    assert B62.shape == (24, 24) and B62.dtype == np.int8
+    assert (B62 == B62.T).all()
+    assert B62.min() == -4 and B62.max() == 11
+    diag = "A4 R5 N6 D6 C9 Q5 E5 G6 H8 I4 L4 K5 M5 F6 P7 S4 T5 W11 Y7 V4".split()
+    for i, d in enumerate(diag):
+        assert swinputs.ALPHABET[i] == d[0] and B62[i, i] == int(d[1:])
+    s = B62[:20, :20].astype(int)
+    # every standard row peaks strictly on the diagonal (needed by the closed forms)
+    for x in range(20):
+        assert all(s[x, y] < s[x, x] for y in range(20) if y != x)
+    assert (B62[23, :23] == -4).all() and B62[23, 23] == 1
+
+
+def test_self_score_is_diagonal_sum():
+    rng = np.random.default_rng(14)
+    for m in (1, 2, 5, 50, 300):
+        q = swinputs.random_residues(m, rng)
+        want = int(sum(int(B62[c, c]) for c in q))
+        assert ocpu.score(q, q, B62, 10, 2) == want
+        if m <= 50:
+            assert oracle.sw_gotoh(q, q, B62, 10, 2) == want
+
+
+def test_embedded_copy_is_diagonal_sum():
+    rng = np.random.default_rng(15)
+    for m in (3, 40, 400):
+        q = swinputs.random_residues(m, rng)
+        x = swinputs.random_residues(int(rng.integers(0, 300)), rng)
+        y = swinputs.random_residues(int(rng.integers(0, 300)), rng)
+        t = np.concatenate([x, q, y])
+        want = int(sum(int(B62[c, c]) for c in q))
+        assert ocpu.score(q, t, B62, 10, 2) == want
+        assert ocpu.score(t, q, B62, 10, 2) == want
+
+
+def test_score_beyond_16_bits():
+    """A 3,000-residue W run against itself scores 33,000 > 32,767."""
+    q = np.full(3000, swinputs.ALPHABET.index("W"), dtype=np.uint8)
+    assert ocpu.score(q, q, B62, 10, 2) == 33000
+
+
+# ----------------------------------------------------------------- invariants
+def test_invariants():
+    rng = np.random.default_rng(16)
+    for _ in range(80):
+        m, n = rng.integers(0, 60, 2)
+        a = rng.integers(0, 24, m).astype(np.uint8)
+        b = rng.integers(0, 24, n).astype(np.uint8)
+        o = int(rng.integers(0, 15)); e = int(rng.integers(0, o + 1))
+        s = ocpu.score(a, b, B62, o, e)
+        assert s >= 0
+        assert s == ocpu.score(b, a, B62, o, e)                    # swap (symmetric S)
+        assert s == ocpu.score(a[::-1].copy(), b[::-1].copy(), B62, o, e)   # reversal
+        lo = max([0] + [int(B62[x, y]) for x in set(a.tolist()) for y in set(b.tolist())])
+        assert lo <= s <= min(m, n) * 11
+        if n > 2:   # substring monotonicity
+            assert ocpu.score(a, b[1:-1], B62, o, e) <= s
+
+
+def test_empty_inputs_score_zero():
+    a = np.zeros(0, dtype=np.uint8)
+    b = swinputs.encode("ACDEFG")
+    assert ocpu.score(a, b, B62, 10, 2) == 0
+    assert ocpu.score(b, a, B62, 10, 2) == 0
+    assert oracle.sw_gotoh(a, b, B62, 10, 2) == 0
+
+
+def test_c_recurrence_matches_python_recurrence_midsize():
+    rng = np.random.default_rng(17)
+    for _ in range(40):
+        m, n = rng.integers(0, 70, 2)
+        a = swinputs.random_residues(m, rng)
+        b = swinputs.random_residues(n, rng)
+        o = int(rng.integers(0, 15)); e = int(rng.integers(0, o + 1))
+        assert ocpu.score(a, b, B62, o, e) == oracle.sw_gotoh(a, b, B62, o, e)
+
+
+def test_threaded_search_matches_single_scores():
+    w = swinputs.config("plain-small")
+    q = w.queries[0][:60]
+    ids = np.arange(0, w.n_seqs, 37)
+    got = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids, threads=4)
+    for t, sid in enumerate(ids[:20]):
+        assert got[t] == ocpu.score(q, w.seq(int(sid)), w.matrix, 10, 2)
+    full = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, threads=3)
+    assert (full[ids] == got).all()
