@@ -1,0 +1,220 @@
+/*
+ * swdb.h - Smith-Waterman protein database search on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper section 2.2, "Smith-Waterman Algorithm", case (b):
+ * database similarity search, one-to-many): for a protein query a = a_1..a_m
+ * and every sequence b = b_1..b_n of a database, return the best local
+ * alignment score
+ *
+ *     SW(a, b) = max(0, max over chains (i_1,j_1) < ... < (i_r,j_r) of
+ *                   sum_t S(a_{i_t}, b_{j_t}) - sum of gap costs),
+ *
+ * where the residues skipped between two matched pairs form one gap in each
+ * sequence and a gap of k >= 1 residues costs gap_open + (k-1) * gap_extend.
+ * The paper's experiments (section 4.1) use BLOSUM62 and gap penalties
+ * "10(2)", i.e. gap_open = 10, gap_extend = 2 under this convention; a caller
+ * who reads "10(2)" as 10 + 2k passes gap_open = 12.
+ *
+ * Scores are exact 32-bit integers, identical to Gotoh's H/E/F recurrence
+ * evaluated in unbounded integers.  Internally most cells are computed in
+ * saturating 16-bit arithmetic; any sequence whose 16-bit score reaches the
+ * saturation limit is rescored exactly in 32-bit arithmetic, and sequences
+ * at least `long_threshold` residues long are scored by a 32-bit intra-task
+ * (anti-diagonal wavefront) kernel (paper section 2.3: inter-task or
+ * intra-task parallelism depending on the sequence length).
+ *
+ * Conventions (all entry points):
+ *  - Residue codes are bytes 0..23 in BLOSUM order
+ *    A R N D C Q E G H I L K M F P S T W Y V B Z X *  (SW_ALPHA = 24).
+ *  - The substitution matrix is int8_t[SW_ALPHA * SW_ALPHA], row-major,
+ *    matrix[q * SW_ALPHA + t] = score of query residue q against database
+ *    residue t.  It is a host pointer, read during the call only.
+ *  - Gap penalties: 0 <= gap_extend <= gap_open <= SW_MAX_GAP.  (With
+ *    gap_open < gap_extend the recurrence and the definition above differ;
+ *    such calls are rejected.)
+ *  - Sizes: query and database sequences shorter than 2^24 residues; at most
+ *    2^31 - 1 database sequences.  Empty queries and empty sequences are
+ *    valid and score 0.
+ *  - Ownership: every input buffer stays owned by the caller and is only read
+ *    during the call (until the stream work completes, for the _async calls).
+ *    Output buffers are caller-allocated.  A database handle owns its device
+ *    memory until sw_db_free.
+ *  - Errors: every function returns SW_OK or an SW_E* code and never throws
+ *    or aborts; sw_last_error() describes the most recent failure on the
+ *    calling thread.  On SW_EINVAL / SW_ERANGE nothing is written to the
+ *    outputs and no work is enqueued.  SW_EDEVICE carries the HIP error
+ *    string.
+ *  - Concurrency: one call at a time per database handle; a concurrent call
+ *    returns SW_EBUSY.  _async calls serialise on the caller's HIP stream.
+ */
+#ifndef SWDB_H_
+#define SWDB_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_ALPHA 24
+#define SW_MAX_GAP (1 << 30)
+#define SW_MAX_LEN ((1 << 24) - 1)
+
+enum sw_status {
+  SW_OK = 0,
+  SW_EINVAL = 1,   /* invalid argument: null pointer, bad code, bad offsets, gaps */
+  SW_ERANGE = 2,   /* a size beyond the documented limits */
+  SW_ENOMEM = 3,   /* device or host allocation failed */
+  SW_EDEVICE = 4,  /* a HIP runtime or kernel error */
+  SW_EBUSY = 5     /* another call is running on the same handle */
+};
+
+typedef struct sw_db sw_db;
+
+/* ------------------------------------------------------------------ database
+ * sw_db_load: copies a protein database to the current HIP device and lays it
+ * out for search (length-sorted, 128 sequences per bin, position-major
+ * interleaved residues - the coalesced layout the paper's 2-D sequence array
+ * gives, section 3.2, figures "matrix_usm"/"matrix_read").
+ *   residues : host, uint8_t[offsets[n_seqs]], codes < SW_ALPHA.
+ *   offsets  : host, int64_t[n_seqs + 1], offsets[0] = 0, non-decreasing;
+ *              sequence i is residues[offsets[i] .. offsets[i+1]).
+ *   n_seqs   : number of sequences, >= 0.
+ *   out_db   : receives the handle (NULL on failure).
+ * sw_db_load_ex additionally sets long_threshold: sequences with at least
+ * this many residues use the intra-task kernel (<= 0 selects the default,
+ * SW_DEFAULT_LONG_THRESHOLD).
+ */
+#define SW_DEFAULT_LONG_THRESHOLD 3072
+int sw_db_load(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+               sw_db** out_db);
+int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+                  int32_t long_threshold, sw_db** out_db);
+
+/* Releases the handle and all its device memory; NULL is a no-op. */
+void sw_db_free(sw_db* db);
+
+/* Database statistics; any output pointer may be NULL. */
+int sw_db_info(const sw_db* db, int64_t* n_seqs, int64_t* n_residues, int32_t* max_len,
+               int64_t* n_long);
+
+/* ------------------------------------------------------------------- search
+ * sw_search: scores one query against every database sequence (synchronous,
+ * host buffers).
+ *   query      : host, uint8_t[query_len], codes < SW_ALPHA.
+ *   out_scores : host, int32_t[n_seqs], in the database's original order.
+ */
+int sw_search(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+              int32_t gap_open, int32_t gap_extend, int32_t* out_scores);
+
+/* sw_search_async: as sw_search with device buffers, enqueued on hip_stream
+ * (a hipStream_t; NULL = the null stream) and returning without waiting.
+ *   d_query      : device, uint8_t[query_len].  Codes are not validated on
+ *                  the device; codes >= SW_ALPHA give unspecified scores (but
+ *                  never out-of-bounds accesses).
+ *   d_out_scores : device, int32_t[n_seqs].
+ * The handle's internal buffers are reused by the next call, so the caller
+ * must not start another call on the handle from a different stream before
+ * this one completes. */
+int sw_search_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
+                    const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                    int32_t* d_out_scores, void* hip_stream);
+
+/* sw_search_batch: many queries against the resident database.
+ *   queries       : host, concatenated codes, query q is
+ *                   queries[query_offsets[q] .. query_offsets[q+1]).
+ *   query_offsets : host, int64_t[n_queries + 1].
+ *   out_scores    : host, int32_t[n_queries * n_seqs], row q = query q. */
+int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offsets,
+                    int32_t n_queries, const int8_t* matrix, int32_t gap_open,
+                    int32_t gap_extend, int32_t* out_scores);
+
+/* sw_search_batch_async: device queries/outputs, host query_offsets. */
+int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* query_offsets,
+                          int32_t n_queries, const int8_t* matrix, int32_t gap_open,
+                          int32_t gap_extend, int32_t* d_out_scores, void* hip_stream);
+
+/* Description of the most recent failure on this thread ("" if none).  The
+ * string stays valid until the next call on the same thread. */
+const char* sw_last_error(void);
+
+/* ------------------------------------------------------------ tuning, stats
+ * sw_set_option: per-handle knobs.  Values outside the listed ranges return
+ * SW_EINVAL.  */
+enum sw_option {
+  SW_OPT_TIMING = 1,      /* 0/1: record HIP events around every kernel */
+  SW_OPT_SAT_LIMIT = 2,   /* 0..32767: 16-bit scores >= limit are rescored in
+                             32 bits (default 32767; 0 rescores everything) */
+  SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto), 16, 32 */
+  SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8 */
+  SW_OPT_INTRA_ROWS = 5   /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
+};
+int sw_set_option(sw_db* db, int32_t key, int64_t value);
+
+/* Counters accumulated over every query searched since the previous
+ * sw_get_stats call (times are 0 for work enqueued with SW_OPT_TIMING off).
+ * Kernel times come from HIP events recorded on the stream each kernel runs
+ * on. */
+typedef struct sw_stats {
+  float ms_total;          /* first query's start to last query's end */
+  float ms_inter;          /* inter-task kernel time, summed over launches */
+  float ms_intra;          /* long-sequence intra-task kernel time, summed */
+  float ms_rescore;        /* 32-bit rescoring kernel time, summed */
+  int32_t n_inter_launches;
+  int32_t n_rescored;      /* sequences rescored in 32 bits for the most
+                              recent query */
+  int64_t inter_cells;     /* real cells (query length x residues) given to
+                              the inter-task kernel */
+  int64_t intra_cells;     /* real cells given to the intra-task kernel */
+  int32_t rows;            /* strip height of the last inter-task launch */
+  int32_t waves;           /* waves per workgroup of the last inter-task launch */
+} sw_stats;
+
+/* Waits for the recorded work, fills *out and resets the counters. */
+int sw_get_stats(sw_db* db, sw_stats* out);
+
+/* ------------------------------------------------------- host-only layout
+ * The database layout, computed without touching any device (the same code
+ * sw_db_load uses).  Sequences are stable-sorted by decreasing length; those
+ * with length >= long_threshold form the long list; the rest fill bins of
+ * SW_BIN_SEQS = 128 consecutive sorted sequences, slot k of a bin being lane
+ * k/2, half k%2.  A bin stores its residues position-major: dword
+ * res_off + (p/4)*128 + k holds positions p..p+3 of slot k (byte p%4 = position
+ * p), padded with code SW_PAD_CODE up to the bin length, a multiple of 4 and
+ * at least SW_MIN_BIN_LEN.
+ */
+#define SW_BIN_SEQS 128
+#define SW_PAD_CODE 24
+#define SW_MIN_BIN_LEN 32
+
+typedef struct sw_plan_info {
+  int64_t n_bins;          /* bins of short sequences */
+  int64_t n_long;          /* sequences in the long list */
+  int64_t packed_dwords;   /* size of the interleaved residue store */
+  int64_t boundary_bytes;  /* inter-task boundary-row scratch for all bins */
+  int32_t max_len;         /* longest sequence */
+  int32_t max_bin_len;     /* longest bin (padded) */
+  int32_t max_long_len;    /* longest sequence in the long list (0 if none) */
+  int32_t long_threshold;  /* the threshold actually used */
+} sw_plan_info;
+
+/* Validates offsets and fills *info.  residues may be NULL (codes are then
+ * not checked). */
+int sw_plan(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+            int32_t long_threshold, sw_plan_info* info);
+
+/* Fills the host layout arrays sized from sw_plan:
+ *   packed   : uint32_t[packed_dwords]
+ *   bin_desc : int64_t[n_bins * 4] = {res_off (dwords), boundary offset
+ *              (16-byte units), length, first slot} per bin
+ *   slot_seq : int32_t[n_bins * 128], original sequence index or -1
+ *   long_ids : int32_t[n_long], original indices, longest first */
+int sw_pack(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+            int32_t long_threshold, uint32_t* packed, int64_t* bin_desc,
+            int32_t* slot_seq, int32_t* long_ids);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWDB_H_ */

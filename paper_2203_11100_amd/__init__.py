@@ -1,0 +1,162 @@
+"""Smith-Waterman protein database search on AMD Instinct MI355X (gfx950).
+
+Python face of libswdb.so (C ABI in include/swdb.h).  `Database` uploads a
+protein database once; `search`, `search_batch` and their device-buffer
+variants score queries against every database sequence with the library's
+HIP kernels.  PyTorch is used only for device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _native
+from ._native import (SwError, SW_ALPHA, SW_BIN_SEQS, SW_PAD_CODE, SW_MIN_BIN_LEN,
+                      SW_DEFAULT_LONG_THRESHOLD, SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS,
+                      SW_OPT_WAVES, SW_OPT_INTRA_ROWS)
+
+__all__ = ["Database", "SwError", "plan", "pack", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
+           "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
+           "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS"]
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data if a.size else None
+    return a.data_ptr()      # torch tensor
+
+
+def _u8(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _i64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _matrix(matrix) -> np.ndarray:
+    m = np.ascontiguousarray(matrix, dtype=np.int8)
+    if m.shape != (SW_ALPHA, SW_ALPHA):
+        raise ValueError("matrix must be int8[24, 24]")
+    return m
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def plan(offsets, long_threshold: int = 0, residues=None) -> dict:
+    """Host-only layout statistics (sw_plan)."""
+    offs = _i64(offsets)
+    res = _u8(residues) if residues is not None else None
+    info = _native.PlanInfo()
+    _native.check(_native.lib().sw_plan(_ptr(res), _ptr(offs), len(offs) - 1, long_threshold,
+                                        ctypes.byref(info)))
+    return {k: getattr(info, k) for k, _ in _native.PlanInfo._fields_}
+
+
+def pack(residues, offsets, long_threshold: int = 0) -> dict:
+    """Host-only database layout arrays (sw_pack)."""
+    res, offs = _u8(residues), _i64(offsets)
+    info = plan(offs, long_threshold, res)
+    packed = np.zeros(max(info["packed_dwords"], 1), dtype=np.uint32)
+    bins = np.zeros((max(info["n_bins"], 1), 4), dtype=np.int64)
+    slots = np.zeros(max(info["n_bins"] * SW_BIN_SEQS, 1), dtype=np.int32)
+    long_ids = np.zeros(max(info["n_long"], 1), dtype=np.int32)
+    _native.check(_native.lib().sw_pack(_ptr(res), _ptr(offs), len(offs) - 1, long_threshold,
+                                        _ptr(packed), _ptr(bins), _ptr(slots), _ptr(long_ids)))
+    return {"info": info, "packed": packed[:info["packed_dwords"]],
+            "bins": bins[:info["n_bins"]], "slot_seq": slots[:info["n_bins"] * SW_BIN_SEQS],
+            "long_ids": long_ids[:info["n_long"]]}
+
+
+class Database:
+    """A protein database resident in device memory (sw_db_load)."""
+
+    def __init__(self, residues, offsets, long_threshold: int = 0):
+        L = _native.lib()
+        self._res = _u8(residues)
+        self._offs = _i64(offsets)
+        h = ctypes.c_void_p()
+        _native.check(L.sw_db_load_ex(_ptr(self._res), _ptr(self._offs), len(self._offs) - 1,
+                                      long_threshold, ctypes.byref(h)))
+        self._h = h
+        self.n_seqs = len(self._offs) - 1
+        self.n_residues = int(self._offs[-1])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _native.lib().sw_db_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def info(self) -> dict:
+        n, r, ml, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64()
+        _native.check(_native.lib().sw_db_info(self._h, ctypes.byref(n), ctypes.byref(r),
+                                               ctypes.byref(ml), ctypes.byref(nl)))
+        return {"n_seqs": n.value, "n_residues": r.value, "max_len": ml.value,
+                "n_long": nl.value}
+
+    def set_option(self, key: int, value: int):
+        _native.check(_native.lib().sw_set_option(self._h, key, int(value)))
+
+    def stats(self) -> dict:
+        st = _native.Stats()
+        _native.check(_native.lib().sw_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _native.Stats._fields_}
+
+    def search(self, query, matrix, gap_open: int = 10, gap_extend: int = 2) -> np.ndarray:
+        """Scores of one query against every sequence (host in, host out)."""
+        q = _u8(query)
+        m = _matrix(matrix)
+        out = np.empty(self.n_seqs, dtype=np.int32)
+        _native.check(_native.lib().sw_search(self._h, _ptr(q), len(q), _ptr(m), gap_open,
+                                              gap_extend, _ptr(out)))
+        return out
+
+    def search_async(self, d_query, matrix, gap_open: int, gap_extend: int, d_out,
+                     stream=None):
+        """Device buffers (torch tensors): d_query uint8[m], d_out int32[n_seqs]."""
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_search_async(
+            self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
+            _ptr(d_out), _stream_handle(stream)))
+
+    def search_batch(self, queries: Sequence, matrix, gap_open: int = 10,
+                     gap_extend: int = 2) -> np.ndarray:
+        """Scores of many queries; returns int32[n_queries, n_seqs]."""
+        qs = [_u8(q) for q in queries]
+        qoffs = np.zeros(len(qs) + 1, dtype=np.int64)
+        np.cumsum([len(q) for q in qs], out=qoffs[1:])
+        cat = np.concatenate(qs) if qs else np.zeros(0, dtype=np.uint8)
+        m = _matrix(matrix)
+        out = np.empty((len(qs), self.n_seqs), dtype=np.int32)
+        _native.check(_native.lib().sw_search_batch(self._h, _ptr(cat), _ptr(qoffs), len(qs),
+                                                    _ptr(m), gap_open, gap_extend, _ptr(out)))
+        return out
+
+    def search_batch_async(self, d_queries, query_offsets, matrix, gap_open: int,
+                           gap_extend: int, d_out, stream=None):
+        qoffs = _i64(query_offsets)
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_search_batch_async(
+            self._h, _ptr(d_queries), _ptr(qoffs), len(qoffs) - 1, _ptr(m), gap_open,
+            gap_extend, _ptr(d_out), _stream_handle(stream)))

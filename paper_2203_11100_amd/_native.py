@@ -1,0 +1,88 @@
+"""ctypes binding of libswdb.so (argument marshalling only).
+
+Every step of a search runs in the library's HIP kernels; this module only
+converts Python/NumPy/torch arguments to the C ABI declared in
+include/swdb.h and turns status codes into exceptions.  It raises if the
+library has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libswdb.so")
+
+SW_OK, SW_EINVAL, SW_ERANGE, SW_ENOMEM, SW_EDEVICE, SW_EBUSY = range(6)
+SW_ALPHA = 24
+SW_BIN_SEQS = 128
+SW_PAD_CODE = 24
+SW_MIN_BIN_LEN = 32
+SW_DEFAULT_LONG_THRESHOLD = 3072
+SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 1, 2, 3, 4, 5
+
+_STATUS_NAMES = {1: "SW_EINVAL", 2: "SW_ERANGE", 3: "SW_ENOMEM", 4: "SW_EDEVICE", 5: "SW_EBUSY"}
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_bins", ctypes.c_int64), ("n_long", ctypes.c_int64),
+                ("packed_dwords", ctypes.c_int64), ("boundary_bytes", ctypes.c_int64),
+                ("max_len", ctypes.c_int32), ("max_bin_len", ctypes.c_int32),
+                ("max_long_len", ctypes.c_int32), ("long_threshold", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_float), ("ms_inter", ctypes.c_float),
+                ("ms_intra", ctypes.c_float), ("ms_rescore", ctypes.c_float),
+                ("n_inter_launches", ctypes.c_int32), ("n_rescored", ctypes.c_int32),
+                ("inter_cells", ctypes.c_int64), ("intra_cells", ctypes.c_int64),
+                ("rows", ctypes.c_int32), ("waves", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol include/swdb.h declares
+P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+SIGNATURES = {
+    "sw_db_load": (ctypes.c_int, [P, P, I64, ctypes.POINTER(P)]),
+    "sw_db_load_ex": (ctypes.c_int, [P, P, I64, I32, ctypes.POINTER(P)]),
+    "sw_db_free": (None, [P]),
+    "sw_db_info": (ctypes.c_int, [P, P, P, P, P]),
+    "sw_search": (ctypes.c_int, [P, P, I32, P, I32, I32, P]),
+    "sw_search_async": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
+    "sw_search_batch": (ctypes.c_int, [P, P, P, I32, P, I32, I32, P]),
+    "sw_search_batch_async": (ctypes.c_int, [P, P, P, I32, P, I32, I32, P, P]),
+    "sw_last_error": (ctypes.c_char_p, []),
+    "sw_set_option": (ctypes.c_int, [P, I32, I64]),
+    "sw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+    "sw_plan": (ctypes.c_int, [P, P, I64, I32, ctypes.POINTER(PlanInfo)]),
+    "sw_pack": (ctypes.c_int, [P, P, I64, I32, P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libswdb.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libswdb.so is not built (%s); run "
+                              "`python -m paper_2203_11100_amd.build`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != SW_OK:
+        msg = lib().sw_last_error()
+        raise SwError(rc, msg.decode() if msg else "")

@@ -1,0 +1,186 @@
+// Inter-task Smith-Waterman/Gotoh kernel: every lane scores two database
+// sequences against the query (paper section 2.2: inter-task parallelism,
+// one independent alignment matrix per processing element, no communication
+// between elements), in packed saturating 16-bit arithmetic.
+//
+// Cells follow Gotoh's recurrence over query rows i and database columns j:
+//   E(i,j) = max(E(i,j-1) - e, H(i,j-1) - o)
+//   F(i,j) = max(F(i-1,j) - e, H(i-1,j) - o)
+//   H(i,j) = max(0, H(i-1,j-1) + S(a_i,b_j), E(i,j), F(i,j)),  score = max H.
+// Two equivalent rewrites make it cheap on packed 16-bit lanes:
+//   * E and F are kept as E' = max(E, 0), F' = max(F, 0).  Because H >= 0,
+//     max(E' - e, H - o, 0) = max(E - e, H - o, 0), so E' obeys the same
+//     update with a floor at 0, and H = max(H_diag + S, E', F') needs no
+//     separate 0.  Unsigned saturating subtraction gives the floor for free.
+//   * H_diag + S uses signed saturating addition.  Every other quantity is
+//     bounded by an earlier H, so the first cell whose true H exceeds 32767
+//     is computed as exactly 32767 and the sequence's maximum becomes 32767;
+//     sequences whose 16-bit maximum reaches the saturation limit are handed
+//     to the exact 32-bit kernel.
+//
+// Work decomposition.  A workgroup owns one bin of 128 length-sorted
+// sequences (lane l holds the sequences of slots 2l and 2l+1 in the low and
+// high 16-bit halves).  The query is cut into strips of R rows; the H and E
+// state of a strip's R rows lives in registers while the strip sweeps every
+// column of the bin.  The bottom row of a strip (H and the F flowing into
+// the next row) is written to a per-bin boundary buffer and read back by the
+// next strip.  The W waves of a workgroup take strips round robin and run
+// as a pipeline: in superstep T, wave w works on columns 4c..4c+3 of its
+// current strip, with c = T - w - q*C (q = its strip round, C = columns/4),
+// and a workgroup barrier separates supersteps.  Strip s therefore reads
+// chunk c one superstep after strip s-1 wrote it, and the buffer can be
+// overwritten in place because every strip reads a chunk before writing it.
+// Splitting one bin's strips over W waves divides its latency by W, which
+// keeps the longest bins from trailing the rest of the grid.
+//
+// The query profile rows of the current strip are staged in LDS, one row of
+// 26 int16 per query position ([row][residue code]).  All lanes read the same
+// row at once, so the addresses fall in 13 consecutive dwords: no bank
+// conflicts.  The two halves' scores are fetched with two 16-bit LDS reads
+// and packed into one register.
+#include "internal.h"
+
+namespace swdb {
+namespace {
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t add_sat(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(
+                                          __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+}
+// per 16-bit half: max(a - b, 0) for a, b read as unsigned
+__device__ __forceinline__ uint32_t sub_floor(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                          __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+__device__ __forceinline__ uint32_t vmax(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(
+                                          __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
+}
+
+template <int R>
+__device__ __forceinline__ void stage_profile(uint32_t* dst, const uint32_t* __restrict__ src,
+                                              int lane) {
+#pragma unroll
+  for (int x = lane; x < R * kProfRowDwords; x += 64) dst[x] = src[x];
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
+  __shared__ uint32_t lprof[W][2][R * kProfRowDwords];
+  __shared__ uint32_t lbest[W][64];
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const BinDesc bin = a.bins[a.bin_begin + blockIdx.x];
+  const int C = (int)(bin.len >> 2);
+  const int S = a.n_strips;
+  const int q_last = (S - 1) / W, w_last = (S - 1) % W;
+  const int T_total = q_last * C + w_last + C;
+  const int my_rounds = (w < S) ? (S - 1 - w) / W + 1 : 0;
+
+  if (my_rounds > 0) stage_profile<R>(&lprof[w][0][0], a.prof + (size_t)w * R * kProfRowDwords, lane);
+  __syncthreads();
+
+  uint32_t H[R], E[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
+  uint32_t best = 0, hdiag = 0;
+  const uint2* __restrict__ rbin = a.res2 + (bin.res_off >> 1);
+  uint4* __restrict__ rbb = a.rb + bin.rb_off;
+  const uint32_t go = a.go2, ge = a.ge2;
+
+  // Wave w idles for w supersteps, then runs its strips back to back, then
+  // idles until the last wave finishes; every wave passes T_total barriers.
+  for (int T = 0; T < w; ++T) __syncthreads();
+  for (int q = 0; q < my_rounds; ++q) {
+    const int s = q * W + w;
+#pragma unroll
+    for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
+    hdiag = 0;
+    const unsigned short* slot = reinterpret_cast<const unsigned short*>(&lprof[w][q & 1][0]);
+    for (int c = 0; c < C; ++c) {
+      if (c == C - 1 && q + 1 < my_rounds)
+        stage_profile<R>(&lprof[w][(q + 1) & 1][0],
+                         a.prof + (size_t)(s + W) * R * kProfRowDwords, lane);
+      const uint2 rr = rbin[c * 64 + lane];
+      uint4* rbp = rbb + (size_t)(c * 64 + lane) * 2;
+      uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+      if (s > 0) { b0 = rbp[0]; b1 = rbp[1]; }
+      const uint32_t up_h[4] = {b0.x, b0.z, b1.x, b1.z};
+      const uint32_t up_f[4] = {b0.y, b0.w, b1.y, b1.w};
+      uint32_t out_h[4], out_f[4];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const unsigned short* plo = slot + ((rr.x >> (8 * jj)) & 0xffu);
+        const unsigned short* phi = slot + ((rr.y >> (8 * jj)) & 0xffu);
+        uint32_t hd = hdiag;
+        hdiag = up_h[jj];
+        uint32_t F = up_f[jj];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+          s16x2 pv;
+          pv.x = (short)plo[k * kProfRowShorts];
+          pv.y = (short)phi[k * kProfRowShorts];
+          const uint32_t p = __builtin_bit_cast(uint32_t, pv);
+          uint32_t h = vmax(vmax(add_sat(hd, p), E[k]), F);
+          hd = H[k];
+          H[k] = h;
+          best = vmax(best, h);
+          const uint32_t t = sub_floor(h, go);
+          E[k] = vmax(sub_floor(E[k], ge), t);
+          F = vmax(sub_floor(F, ge), t);
+        }
+        out_h[jj] = H[R - 1];
+        out_f[jj] = F;
+      }
+      if (s < S - 1) {
+        rbp[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
+        rbp[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+      }
+      __syncthreads();
+    }
+  }
+  for (int T = w + my_rounds * C; T < T_total; ++T) __syncthreads();
+
+  lbest[w][lane] = best;
+  __syncthreads();
+  if (w != 0) return;
+#pragma unroll
+  for (int x = 1; x < W; ++x) best = vmax(best, lbest[x][lane]);
+  const int64_t slot0 = bin.slot0 + 2 * lane;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int sid = a.slot_seq[slot0 + half];
+    if (sid < 0) continue;
+    const int score = (int)((best >> (16 * half)) & 0xffffu);
+    if (score >= a.sat_limit) {
+      const int idx = atomicAdd(a.flag_count, 1);
+      a.flag_list[idx] = sid;
+    } else {
+      a.out[sid] = score;
+    }
+  }
+}
+
+template <int R, int W>
+hipError_t launch_rw(int n_bins, const InterArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_inter_i16<R, W>), dim3(n_bins), dim3(64 * W), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_t s) {
+  if (n_bins <= 0) return hipSuccess;
+#define SWDB_CASE(r, w) \
+  if (R == r && W == w) return launch_rw<r, w>(n_bins, a, s);
+  SWDB_CASE(16, 1) SWDB_CASE(16, 2) SWDB_CASE(16, 4) SWDB_CASE(16, 8)
+  SWDB_CASE(32, 1) SWDB_CASE(32, 2) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+#undef SWDB_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace swdb

@@ -1,0 +1,256 @@
+"""GPU parity: library scores vs the CPU oracle, bit-exact.
+
+Every test calls the HIP path through the C ABI (paper_2203_11100_amd ->
+libswdb.so) and compares each score with oracle/ (plain scalar Gotoh in C).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.cpu as ocpu
+import swinputs
+
+pytestmark = pytest.mark.gpu
+
+B62 = swinputs.blosum62()
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def sw():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2203_11100_amd as lib
+    return lib
+
+
+def _oracle(q, res, offs, S=B62, go=10, ge=2, ids=None):
+    return ocpu.search(q, res, offs, S, go, ge, ids=ids)
+
+
+def _ragged_db(seed=0):
+    rng = np.random.default_rng(seed)
+    lengths = np.concatenate([
+        [0, 0, 1, 2, 3, 4, 5, 7, 8, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257],
+        rng.integers(20, 700, 1200),
+        [1500, 2100],
+    ]).astype(np.int64)
+    rng.shuffle(lengths)
+    return swinputs.make_database(lengths, rng)
+
+
+def test_plain_small_workload(sw):
+    w = swinputs.config("plain-small")
+    say("plain-small: 2000 seqs, m=144")
+    with sw.Database(w.residues, w.offsets) as db:
+        got = db.search(w.queries[0], w.matrix, 10, 2)
+    want = _oracle(w.queries[0], w.residues, w.offsets)
+    assert (got == want).all(), np.nonzero(got != want)[0][:10]
+
+
+@pytest.mark.parametrize("m", [1, 2, 15, 16, 17, 31, 32, 33, 100, 255, 257, 600])
+def test_ragged_database_query_lengths(sw, m):
+    res, offs = _ragged_db()
+    q = swinputs.random_residues(m, np.random.default_rng(m))
+    say("ragged db, m=%d" % m)
+    with sw.Database(res, offs) as db:
+        got = db.search(q, B62, 10, 2)
+    assert (got == _oracle(q, res, offs)).all()
+
+
+@pytest.mark.parametrize("rows", [16, 32])
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+def test_strip_and_wave_options(sw, rows, waves):
+    res, offs = _ragged_db(1)
+    q = swinputs.random_residues(333, np.random.default_rng(5))
+    say("rows=%d waves=%d" % (rows, waves))
+    with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_ROWS, rows)
+        db.set_option(sw.SW_OPT_WAVES, waves)
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+    assert st["rows"] == rows and st["waves"] == waves
+    assert (got == _oracle(q, res, offs)).all()
+
+
+@pytest.mark.parametrize("intra_rows", [2, 4, 8])
+@pytest.mark.parametrize("t_long", [1, 100])
+def test_intra_task_path(sw, intra_rows, t_long):
+    res, offs = _ragged_db(2)
+    q = swinputs.random_residues(700, np.random.default_rng(6))
+    say("t_long=%d intra_rows=%d" % (t_long, intra_rows))
+    with sw.Database(res, offs, long_threshold=t_long) as db:
+        assert db.info()["n_long"] > 0
+        db.set_option(sw.SW_OPT_INTRA_ROWS, intra_rows)
+        got = db.search(q, B62, 10, 2)
+    assert (got == _oracle(q, res, offs)).all()
+
+
+@pytest.mark.parametrize("limit", [0, 40, 32767])
+def test_forced_rescoring(sw, limit):
+    res, offs = _ragged_db(3)
+    q = swinputs.random_residues(300, np.random.default_rng(7))
+    say("sat limit %d" % limit)
+    with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+    want = _oracle(q, res, offs)
+    assert (got == want).all()
+    if limit == 0:
+        assert st["n_rescored"] == len(want)
+    if limit == 40:
+        assert st["n_rescored"] == int((want >= 40).sum())
+
+
+def test_planted_overflow_in_short_bins(sw):
+    """Scores above 32767 inside the 16-bit kernel's bins are rescored exactly."""
+    rng = np.random.default_rng(8)
+    W = swinputs.ALPHABET.index("W")
+    q = np.concatenate([np.full(2700, W, np.uint8), swinputs.random_residues(1200, rng)])
+    lengths = rng.integers(50, 900, 300).astype(np.int64)
+    res, offs = swinputs.make_database(lengths, rng)
+    seqs = [res[offs[i]:offs[i + 1]] for i in range(len(lengths))]
+    planted = [5, 77, 200]
+    for i in planted:
+        seqs[i] = np.concatenate([swinputs.random_residues(30, rng), q, swinputs.random_residues(9, rng)])
+    lens = np.array([len(s) for s in seqs], dtype=np.int64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offs[1:])
+    res = np.concatenate(seqs)
+    diag = int(sum(int(B62[c, c]) for c in q))
+    assert diag > 32767
+    say("planted overflow")
+    with sw.Database(res, offs, long_threshold=10**6) as db:
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+    assert st["n_rescored"] >= len(planted)
+    for i in planted:
+        assert got[i] == diag
+    assert (got == _oracle(q, res, offs)).all()
+
+
+@pytest.mark.parametrize("gaps", [(0, 0), (5, 5), (11, 1), (40, 1), (1000, 1000), (12, 2)])
+def test_gap_penalties(sw, gaps):
+    res, offs = _ragged_db(4)
+    q = swinputs.random_residues(180, np.random.default_rng(9))
+    say("gaps", gaps)
+    with sw.Database(res, offs, long_threshold=1000) as db:
+        got = db.search(q, B62, *gaps)
+    assert (got == _oracle(q, res, offs, B62, *gaps)).all()
+
+
+def test_random_asymmetric_full_range_matrix(sw):
+    rng = np.random.default_rng(10)
+    S = rng.integers(-128, 128, size=(24, 24)).astype(np.int8)
+    res, offs = _ragged_db(5)
+    q = swinputs.random_residues(400, rng)
+    say("random matrix")
+    with sw.Database(res, offs, long_threshold=1000) as db:
+        got = db.search(q, S, 13, 3)
+    assert (got == _oracle(q, res, offs, S, 13, 3)).all()
+
+
+def test_empty_query_and_empty_database(sw):
+    res, offs = _ragged_db(6)
+    with sw.Database(res, offs) as db:
+        got = db.search(np.zeros(0, np.uint8), B62, 10, 2)
+    assert (got == 0).all()
+    with sw.Database(np.zeros(0, np.uint8), np.zeros(1, np.int64)) as db:
+        assert db.search(swinputs.encode("ACDE"), B62, 10, 2).shape == (0,)
+
+
+def test_batch_and_async_match_single(sw):
+    import torch
+    res, offs = _ragged_db(7)
+    rng = np.random.default_rng(11)
+    qs = [swinputs.random_residues(int(m), rng) for m in (0, 50, 144, 700, 31)]
+    say("batch/async")
+    with sw.Database(res, offs, long_threshold=600) as db:
+        single = np.stack([db.search(q, B62, 10, 2) for q in qs])
+        batch = db.search_batch(qs, B62, 10, 2)
+        assert (single == batch).all()
+        cat = torch.from_numpy(np.concatenate(qs)).cuda()
+        qoffs = np.zeros(len(qs) + 1, np.int64)
+        np.cumsum([len(q) for q in qs], out=qoffs[1:])
+        d_out = torch.full((len(qs), db.n_seqs), -1, dtype=torch.int32, device="cuda")
+        db.search_batch_async(cat, qoffs, B62, 10, 2, d_out)
+        torch.cuda.synchronize()
+        assert (d_out.cpu().numpy() == single).all()
+        d1 = torch.full((db.n_seqs,), -1, dtype=torch.int32, device="cuda")
+        db.search_async(torch.from_numpy(qs[3]).cuda(), B62, 10, 2, d1)
+        torch.cuda.synchronize()
+        assert (d1.cpu().numpy() == single[3]).all()
+    for q, row in zip(qs, single):
+        assert (row == _oracle(q, res, offs)).all()
+
+
+def test_invalid_arguments_write_nothing(sw):
+    res, offs = _ragged_db(8)
+    L = sw._native.lib()
+    with sw.Database(res, offs) as db:
+        q = swinputs.encode("ACDEFGHIK")
+        out = np.full(db.n_seqs, -7, dtype=np.int32)
+        for go, ge in ((2, 3), (-1, 0), ((1 << 30) + 1, 0)):
+            rc = L.sw_search(db._h, q.ctypes.data, len(q), B62.ctypes.data, go, ge, out.ctypes.data)
+            assert rc in (sw._native.SW_EINVAL, sw._native.SW_ERANGE)
+        bad = q.copy(); bad[3] = 24
+        rc = L.sw_search(db._h, bad.ctypes.data, len(bad), B62.ctypes.data, 10, 2, out.ctypes.data)
+        assert rc == sw._native.SW_EINVAL
+        assert (out == -7).all()
+        with pytest.raises(sw.SwError):
+            db.set_option(sw.SW_OPT_ROWS, 7)
+
+
+def test_repeatable(sw):
+    w = swinputs.config("plain-small")
+    with sw.Database(w.residues, w.offsets) as db:
+        a = db.search(w.queries[0], w.matrix, 10, 2)
+        for _ in range(3):
+            assert (db.search(w.queries[0], w.matrix, 10, 2) == a).all()
+
+
+def test_long_mix_workload_scaled(sw):
+    w = swinputs.config("long-mix", scale=0.05)
+    qs = [w.queries[0], w.queries[4], w.queries[9]]     # m = 1000, 5000, 10000
+    say("long-mix 5%%: %d seqs, %d long" % (w.n_seqs, int((np.diff(w.offsets) >= 10000).sum())))
+    with sw.Database(w.residues, w.offsets) as db:
+        got = db.search_batch(qs, w.matrix, 10, 2)
+    for q, row in zip(qs, got):
+        assert (row == _oracle(q, w.residues, w.offsets)).all()
+    diag = int(sum(int(B62[c, c]) for c in qs[2]))
+    assert diag > 32767
+    assert (got[2][w.planted] == diag).all()
+
+
+def test_full_size_plain_workload_sampled(sw):
+    """All 20 queries on the full 200,000-sequence database, in the launch
+    configuration the benchmark times; every score of a sample spanning the
+    length distribution (incl. the longest sequences) checked by the oracle,
+    plus properties that hold for every score."""
+    import torch
+    w = swinputs.config("plain")
+    lens = np.diff(w.offsets)
+    order = np.argsort(-lens, kind="stable")
+    rng = np.random.default_rng(12)
+    ids = np.unique(np.concatenate([order[:6], order[-6:], rng.choice(w.n_seqs, 60, replace=False)]))
+    say("full plain workload: %d seqs, %d residues" % (w.n_seqs, w.n_residues))
+    with sw.Database(w.residues, w.offsets) as db:
+        outs = []
+        for q in w.queries:
+            d_out = torch.empty(db.n_seqs, dtype=torch.int32, device="cuda")
+            db.search_async(torch.from_numpy(q).cuda(), w.matrix, 10, 2, d_out)
+            outs.append(d_out)
+        torch.cuda.synchronize()
+        got = np.stack([o.cpu().numpy() for o in outs])
+    for qi, q in enumerate(w.queries):
+        want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
+        assert (got[qi][ids] == want).all(), (qi, ids[got[qi][ids] != want][:5])
+        # every score: 0 <= s <= min(m, n) * 11, and at least the best single pair
+        assert (got[qi] >= 0).all()
+        assert (got[qi] <= np.minimum(len(q), lens) * 11).all()
+    say("sampled %d x %d scores ok" % (len(w.queries), len(ids)))
