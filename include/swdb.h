@@ -147,7 +147,8 @@ enum sw_option {
                              32 bits (default 32767; 0 rescores everything) */
   SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto), 16, 32 */
   SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8 */
-  SW_OPT_INTRA_ROWS = 5   /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
+  SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
+  SW_OPT_INTRA_WAVES = 6  /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
 };
 int sw_set_option(sw_db* db, int32_t key, int64_t value);
 
@@ -185,7 +186,7 @@ int sw_get_stats(sw_db* db, sw_stats* out);
  */
 #define SW_BIN_SEQS 128
 #define SW_PAD_CODE 24
-#define SW_MIN_BIN_LEN 32
+#define SW_MIN_BIN_LEN 64
 
 typedef struct sw_plan_info {
   int64_t n_bins;          /* bins of short sequences */

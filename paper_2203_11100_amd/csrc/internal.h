@@ -28,7 +28,7 @@ constexpr int kProfRowDwords = 13;
 // Score given to padding (pad code, and query rows past the end).  Any value
 // <= 0 keeps padded cells from raising a maximum.
 constexpr int kPadScore = -64;
-// Intra-task profile has the 24 codes plus the pad code.
+// Intra-task profile (int8, [code][row]) has the 24 codes plus the pad code.
 constexpr int kIntraCodes = 25;
 
 struct InterArgs {
@@ -52,9 +52,9 @@ struct IntraArgs {
   const int32_t* items;       // sequence ids to score
   const int32_t* count_ptr;   // device item count (rescoring) or nullptr
   int32_t count;              // host item count when count_ptr == nullptr
-  const int16_t* prof2;       // [25][m_pad2]
-  int32_t m_pad2;
-  int32_t n_pass;
+  const int8_t* prof2;        // [25][m_pad2] int8
+  int32_t m_pad2;             // multiple of 64*R for every R used with it
+  int32_t n_pass;             // passes of 64*R rows covering the query
   int32_t go, ge;
   int2* scratch;              // per-workgroup boundary rows
   int64_t scratch_stride;     // int2 elements per workgroup
@@ -63,11 +63,10 @@ struct IntraArgs {
 
 // Kernel launchers (return hipSuccess or the launch error).
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
-                          int m_pad, int16_t* prof2, int m_pad2, int32_t* flag_count,
+                          int m_pad, int8_t* prof2, int m_pad2, int32_t* flag_count,
                           hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_t s);
-hipError_t launch_intra(int RR, int grid, const IntraArgs& a, hipStream_t s);
-int intra_lds_bytes(int RR);
+hipError_t launch_intra(int RR, int W2, int grid, const IntraArgs& a, hipStream_t s);
 
 }  // namespace swdb

@@ -26,10 +26,11 @@
 // the next row) is written to a per-bin boundary buffer and read back by the
 // next strip.  The W waves of a workgroup take strips round robin and run
 // as a pipeline: in superstep T, wave w works on columns 4c..4c+3 of its
-// current strip, with c = T - w - q*C (q = its strip round, C = columns/4),
-// and a workgroup barrier separates supersteps.  Strip s therefore reads
-// chunk c one superstep after strip s-1 wrote it, and the buffer can be
-// overwritten in place because every strip reads a chunk before writing it.
+// current strip, with c = T - 2w - q*C (q = its strip round, C = columns/4),
+// and a workgroup barrier separates supersteps.  Strip s works on chunk c two
+// supersteps after strip s-1, so it can prefetch the chunk's residues and
+// boundary values one superstep ahead; the buffer can be overwritten in place
+// because every strip reads a chunk before writing it.
 // Splitting one bin's strips over W waves divides its latency by W, which
 // keeps the longest bins from trailing the rest of the grid.
 //
@@ -60,16 +61,12 @@ __device__ __forceinline__ uint32_t vmax(uint32_t a, uint32_t b) {
                                           __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
 }
 
-template <int R>
-__device__ __forceinline__ void stage_profile(uint32_t* dst, const uint32_t* __restrict__ src,
-                                              int lane) {
-#pragma unroll
-  for (int x = lane; x < R * kProfRowDwords; x += 64) dst[x] = src[x];
-}
-
 template <int R, int W>
 __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
-  __shared__ uint32_t lprof[W][2][R * kProfRowDwords];
+  constexpr int D = 2;   // superstep skew between consecutive waves
+  constexpr int kSlot = R * kProfRowDwords;
+  constexpr int kStage = (kSlot + 63) / 64;
+  __shared__ uint32_t lprof[W][2][kSlot];
   __shared__ uint32_t lbest[W][64];
 
   const int lane = threadIdx.x & 63;
@@ -78,54 +75,88 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
   const int C = (int)(bin.len >> 2);
   const int S = a.n_strips;
   const int q_last = (S - 1) / W, w_last = (S - 1) % W;
-  const int T_total = q_last * C + w_last + C;
+  const int T_total = q_last * C + D * w_last + C;
   const int my_rounds = (w < S) ? (S - 1 - w) / W + 1 : 0;
 
-  if (my_rounds > 0) stage_profile<R>(&lprof[w][0][0], a.prof + (size_t)w * R * kProfRowDwords, lane);
+  if (my_rounds > 0) {
+    const uint32_t* src = a.prof + (size_t)w * kSlot;
+#pragma unroll
+    for (int x = lane; x < kSlot; x += 64) lprof[w][0][x] = src[x];
+  }
   __syncthreads();
 
-  uint32_t H[R], E[R];
-#pragma unroll
-  for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
-  uint32_t best = 0, hdiag = 0;
   const uint2* __restrict__ rbin = a.res2 + (bin.res_off >> 1);
   uint4* __restrict__ rbb = a.rb + bin.rb_off;
   const uint32_t go = a.go2, ge = a.ge2;
 
-  // Wave w idles for w supersteps, then runs its strips back to back, then
-  // idles until the last wave finishes; every wave passes T_total barriers.
-  for (int T = 0; T < w; ++T) __syncthreads();
+  // inputs of the next chunk, fetched one superstep ahead
+  uint2 rr_n = make_uint2(0, 0);
+  uint4 b0_n = make_uint4(0, 0, 0, 0), b1_n = make_uint4(0, 0, 0, 0);
+  auto fetch = [&](int s, int c) {
+    rr_n = rbin[c * 64 + lane];
+    if (s > 0) {
+      const uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
+      b0_n = p[0];
+      b1_n = p[1];
+    } else {
+      b0_n = make_uint4(0, 0, 0, 0);
+      b1_n = make_uint4(0, 0, 0, 0);
+    }
+  };
+
+  uint32_t H[R], E[R];
+  uint32_t best = 0;
+
+  // Wave w idles for D*w supersteps (prefetching in the last one), runs its
+  // strips back to back, then idles until the last wave finishes; every wave
+  // passes T_total barriers.  With the skew D = 2, the chunk a wave prefetches
+  // in superstep T was written by the previous strip's wave in T-1 or
+  // earlier (bins have at least 2W chunks, which covers the wrap from the
+  // last wave to the first).
+  if (w == 0 && my_rounds > 0) fetch(0, 0);
+  for (int T = 0; T < D * w; ++T) {
+    if (T == D * w - 1 && my_rounds > 0) fetch(w, 0);
+    __syncthreads();
+  }
   for (int q = 0; q < my_rounds; ++q) {
     const int s = q * W + w;
 #pragma unroll
     for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
-    hdiag = 0;
+    uint32_t hdiag = 0;
     const unsigned short* slot = reinterpret_cast<const unsigned short*>(&lprof[w][q & 1][0]);
+    const bool more = q + 1 < my_rounds;
     for (int c = 0; c < C; ++c) {
-      if (c == C - 1 && q + 1 < my_rounds)
-        stage_profile<R>(&lprof[w][(q + 1) & 1][0],
-                         a.prof + (size_t)(s + W) * R * kProfRowDwords, lane);
-      const uint2 rr = rbin[c * 64 + lane];
-      uint4* rbp = rbb + (size_t)(c * 64 + lane) * 2;
-      uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
-      if (s > 0) { b0 = rbp[0]; b1 = rbp[1]; }
-      const uint32_t up_h[4] = {b0.x, b0.z, b1.x, b1.z};
-      const uint32_t up_f[4] = {b0.y, b0.w, b1.y, b1.w};
+      const uint2 rr = rr_n;
+      const uint32_t up_h[4] = {b0_n.x, b0_n.z, b1_n.x, b1_n.z};
+      const uint32_t up_f[4] = {b0_n.y, b0_n.w, b1_n.y, b1_n.w};
+      if (c + 1 < C) fetch(s, c + 1);
+      else if (more) fetch(s + W, 0);
+      // next strip's profile: global loads now, LDS stores after the compute
+      const bool stage = more && c == C - 1;
+      uint32_t st[kStage];
+      if (stage) {
+        const uint32_t* src = a.prof + (size_t)(s + W) * kSlot;
+#pragma unroll
+        for (int x = 0; x < kStage; ++x)
+          if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
+      }
       uint32_t out_h[4], out_f[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
+        // two 16-bit LDS reads per row, packed into one register (16-bit
+        // loads on gfx950 zero the other half, so the packing costs one op)
         const unsigned short* plo = slot + ((rr.x >> (8 * jj)) & 0xffu);
         const unsigned short* phi = slot + ((rr.y >> (8 * jj)) & 0xffu);
+        uint32_t p[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+          p[k] = (uint32_t)plo[k * kProfRowShorts] | ((uint32_t)phi[k * kProfRowShorts] << 16);
         uint32_t hd = hdiag;
         hdiag = up_h[jj];
         uint32_t F = up_f[jj];
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-          s16x2 pv;
-          pv.x = (short)plo[k * kProfRowShorts];
-          pv.y = (short)phi[k * kProfRowShorts];
-          const uint32_t p = __builtin_bit_cast(uint32_t, pv);
-          uint32_t h = vmax(vmax(add_sat(hd, p), E[k]), F);
+          uint32_t h = vmax(vmax(add_sat(hd, p[k]), E[k]), F);
           hd = H[k];
           H[k] = h;
           best = vmax(best, h);
@@ -137,13 +168,19 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
         out_f[jj] = F;
       }
       if (s < S - 1) {
-        rbp[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
-        rbp[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+        uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
+        p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
+        p[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+      }
+      if (stage) {
+#pragma unroll
+        for (int x = 0; x < kStage; ++x)
+          if (x * 64 + lane < kSlot) lprof[w][(q + 1) & 1][x * 64 + lane] = st[x];
       }
       __syncthreads();
     }
   }
-  for (int T = w + my_rounds * C; T < T_total; ++T) __syncthreads();
+  for (int T = D * w + my_rounds * C; T < T_total; ++T) __syncthreads();
 
   lbest[w][lane] = best;
   __syncthreads();

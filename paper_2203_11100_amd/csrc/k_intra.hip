@@ -3,27 +3,40 @@
 // processing elements work on one alignment matrix and neighbours exchange
 // border elements; section 2.3: SW#db switches to it by sequence length).
 //
-// One wave scores one (query, database sequence) pair.  Lane l owns R
-// consecutive query rows of the current pass (a pass covers 64*R rows) and
-// the wave sweeps the database sequence as an anti-diagonal wavefront: at
-// step t lane l computes column j = t - l of its rows, so lane l receives the
-// H and F values of row (top - 1) for column j from lane l-1, which computed
-// them in the previous step.  The exchange is one cross-lane DPP move per
-// value (wave_shr:1); no LDS and no barrier are needed inside the wave.
-// Lane 0 takes its inputs from the previous pass's bottom row (kept in a
-// per-workgroup global buffer), and the last lane's bottom row is collected
-// for the next pass; residue codes and the boundary row are fed in 64
-// columns at a time and shifted down the wave one lane per step.
+// One workgroup of W2 waves scores one (query, database sequence) pair at a
+// time.  The query is cut into passes of 64*R rows; lane l of a wave owns R
+// consecutive rows of its pass and the wave sweeps the database sequence as
+// an anti-diagonal wavefront: at step t lane l computes column j = t - l of
+// its rows, so it receives the H and F values of row (top - 1) for column j
+// from lane l-1, which computed them in the previous step.  That exchange is
+// one cross-lane DPP move per value (wave_shr:1), with no LDS and no barrier
+// inside the wave.  Lane 0 is fed the previous pass's bottom row (H and the F
+// flowing into the next row) from a per-workgroup buffer, and the last lane's
+// bottom row is collected (wave_shl:1) for the next pass.  Residue codes and
+// the boundary row enter 64 columns at a time and move down the wave one
+// lane per step.
 //
-// Cells use the exact recurrence in 32-bit integers, E and F kept as
-// max(E, 0) and max(F, 0) (equivalent because H >= 0; see the inter-task
-// kernel), so H = max(H_diag + S, E, F) is one three-input maximum.
-// Columns before a lane's first column and after the sequence's end see the
-// pad code, whose profile score is <= 0, so they never raise the maximum.
+// The W2 waves take passes round robin and run as a pipeline, like the
+// strips of the inter-task kernel: a superstep is 64 steps, wave w runs
+// superstep c of its pass q*W2 + w in workgroup superstep T = q*C2 + 3w + c,
+// and workgroup barriers separate supersteps.  Pass p needs columns
+// 64c..64c+63 of pass p-1's bottom row, which are complete once pass p-1 has
+// finished its superstep c+1; the skew of 3 supersteps leaves one superstep
+// for the prefetch of those columns.  Every pass has at least 3*W2 supersteps
+// (short sequences are padded with pad columns), which covers the wrap from
+// the last wave to the first.  The boundary buffer is overwritten in place:
+// a pass reads each column before it writes it.
 //
-// The pass's profile is staged in LDS as [code][row]: lanes read their R rows
-// for their own residue code, R*2 contiguous bytes at code*64R*2 + 2Rl, which
-// keeps the 64 reads of a wave in distinct banks whatever the codes are.
+// Cells use the exact recurrence in 32-bit integers with E and F kept as
+// max(E, 0), max(F, 0) (equivalent because H >= 0; see the inter-task
+// kernel), so H = max(H_diag + S, E, F) is one three-input maximum.  Columns
+// before a lane's first column and after the sequence's end see the pad code,
+// whose profile score is <= 0, so they never raise the maximum.
+//
+// Each wave stages its pass's profile in LDS as int8 [code][row]: a lane
+// reads its R rows for its own residue code, R contiguous bytes at
+// code*64R + R*l, so the 64 reads of a wave cover consecutive bytes of one
+// code row each and never conflict on banks.
 #include "internal.h"
 
 namespace swdb {
@@ -31,6 +44,7 @@ namespace {
 
 constexpr int kWaveShr1 = 0x138;  // DPP wave_shr:1  (lane l <- lane l-1)
 constexpr int kWaveShl1 = 0x130;  // DPP wave_shl:1  (lane l <- lane l+1)
+constexpr int kSkew = 3;          // supersteps between consecutive passes
 
 // lane l <- lane l-1; lane 0 keeps `first`
 __device__ __forceinline__ int shr_in(int v, int first) {
@@ -42,74 +56,108 @@ __device__ __forceinline__ int shl_in(int v, int last) {
 }
 
 template <int R> struct ProfVec;
-template <> struct ProfVec<2> { typedef uint32_t T; };
-template <> struct ProfVec<4> { typedef uint2 T; };
-template <> struct ProfVec<8> { typedef uint4 T; };
+template <> struct ProfVec<2> { typedef uint16_t T; };
+template <> struct ProfVec<4> { typedef uint32_t T; };
+template <> struct ProfVec<8> { typedef uint2 T; };
 
+// sign-extends the R int8 profile values of a lane
 template <int R>
 __device__ __forceinline__ void unpack_profile(const typename ProfVec<R>::T& v, int (&p)[R]);
 template <>
-__device__ __forceinline__ void unpack_profile<2>(const uint32_t& v, int (&p)[2]) {
-  p[0] = (int)(short)(v & 0xffffu);
-  p[1] = (int)v >> 16;
+__device__ __forceinline__ void unpack_profile<2>(const uint16_t& v, int (&p)[2]) {
+  const int x = (int)v;
+  p[0] = (x << 24) >> 24;
+  p[1] = (x << 16) >> 24;
 }
 template <>
-__device__ __forceinline__ void unpack_profile<4>(const uint2& v, int (&p)[4]) {
-  p[0] = (int)(short)(v.x & 0xffffu); p[1] = (int)v.x >> 16;
-  p[2] = (int)(short)(v.y & 0xffffu); p[3] = (int)v.y >> 16;
+__device__ __forceinline__ void unpack_profile<4>(const uint32_t& v, int (&p)[4]) {
+  const int x = (int)v;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) p[k] = (x << (24 - 8 * k)) >> 24;
 }
 template <>
-__device__ __forceinline__ void unpack_profile<8>(const uint4& v, int (&p)[8]) {
-  p[0] = (int)(short)(v.x & 0xffffu); p[1] = (int)v.x >> 16;
-  p[2] = (int)(short)(v.y & 0xffffu); p[3] = (int)v.y >> 16;
-  p[4] = (int)(short)(v.z & 0xffffu); p[5] = (int)v.z >> 16;
-  p[6] = (int)(short)(v.w & 0xffffu); p[7] = (int)v.w >> 16;
+__device__ __forceinline__ void unpack_profile<8>(const uint2& v, int (&p)[8]) {
+  const int x = (int)v.x, y = (int)v.y;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    p[k] = (x << (24 - 8 * k)) >> 24;
+    p[k + 4] = (y << (24 - 8 * k)) >> 24;
+  }
 }
 
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-template <int R>
-__global__ __launch_bounds__(64) void k_intra_i32(IntraArgs a) {
-  constexpr int ROWS = 64 * R;                 // query rows per pass
-  extern __shared__ __align__(16) int16_t lprof[];   // [kIntraCodes][ROWS]
+template <int R, int W2>
+__global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
+  constexpr int ROWS = 64 * R;   // query rows per pass
+  __shared__ __align__(16) int8_t lprof_all[W2][kIntraCodes * ROWS];
+  __shared__ int lbest[W2];
   typedef typename ProfVec<R>::T PV;
 
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  int8_t* lprof = &lprof_all[w][0];
   const int count = a.count_ptr ? *a.count_ptr : a.count;
   int2* __restrict__ rb = a.scratch + (size_t)blockIdx.x * a.scratch_stride;
   const int go = a.go, ge = a.ge;
+  const int P = a.n_pass;
+  const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
+  const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
 
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
     const int sid = a.items[it];
     const int64_t b0 = a.offs[sid];
     const int n = (int)(a.offs[sid + 1] - b0);
     const uint8_t* __restrict__ bseq = a.res + b0;
+    // supersteps per pass: n + 63 steps, at least kSkew*W2 (see above)
+    const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
+    const int T_total = q_last * C2 + kSkew * w_last + C2;
+
+    // feeder values of the next superstep, fetched one superstep ahead
+    int fcode_n = SW_PAD_CODE, fh_n = 0, ff_n = 0;
+    auto fetch = [&](int p, int c) {
+      const int jf = c * 64 + lane;
+      fcode_n = jf < n ? (int)bseq[jf] : SW_PAD_CODE;
+      fh_n = 0;
+      ff_n = 0;
+      if (p > 0 && jf < n) {
+        const int2 v = rb[jf];
+        fh_n = v.x;
+        ff_n = v.y;
+      }
+    };
+
     int best = 0;
-    const int n_super = (n + 63 + 63) >> 6;   // steps n + 63, 64 per superstep
-    for (int p = 0; p < a.n_pass; ++p) {
-      __syncthreads();   // the previous pass is done reading lprof
-      {
+    if (w == 0 && my_rounds > 0) fetch(0, 0);
+    for (int T = 0; T < kSkew * w; ++T) {
+      if (T == kSkew * w - 1 && my_rounds > 0) fetch(w, 0);
+      __syncthreads();
+    }
+    for (int q = 0; q < my_rounds; ++q) {
+      const int p = q * W2 + w;
+      const bool more = q + 1 < my_rounds;
+      const bool last_pass = p == P - 1;
+      {  // stage this pass's profile rows (read back only by this wave)
         const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.prof2);
         uint4* dst = reinterpret_cast<uint4*>(lprof);
-        const int per_code = ROWS / 8;         // uint4 per code row
-        const int src_stride = a.m_pad2 / 8;
+        constexpr int per_code = ROWS / 16;           // uint4 per code row
+        const int src_stride = a.m_pad2 / 16;
         for (int x = lane; x < kIntraCodes * per_code; x += 64) {
           const int code = x / per_code, r = x - code * per_code;
           dst[x] = src[(size_t)code * src_stride + (size_t)p * per_code + r];
         }
+        // LDS operations of one wave execute in order; keep the compiler
+        // from moving the reads below above these writes
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
       }
-      __syncthreads();
-      const bool last_pass = (p == a.n_pass - 1);
-      const bool first_pass = (p == 0);
       int H[R], E[R];
 #pragma unroll
       for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
       int hdiag = 0, code = SW_PAD_CODE, hbot = 0, fbot = 0;
-      for (int c = 0; c < n_super; ++c) {
-        const int jf = c * 64 + lane;
-        int fcode = jf < n ? (int)bseq[jf] : SW_PAD_CODE;
-        int fh = 0, ff = 0;
-        if (!first_pass && jf < n) { const int2 v = rb[jf]; fh = v.x; ff = v.y; }
+      for (int c = 0; c < C2; ++c) {
+        int fcode = fcode_n, fh = fh_n, ff = ff_n;
+        if (c + 1 < C2) fetch(p, c + 1);
+        else if (more) fetch(p + W2, 0);
         int collh = 0, collf = 0;
         for (int tau = 0; tau < 64; ++tau) {
           code = shr_in(code, fcode);
@@ -141,29 +189,43 @@ __global__ __launch_bounds__(64) void k_intra_i32(IntraArgs a) {
         }
         const int jo = c * 64 + lane - 63;
         if (!last_pass && jo >= 0 && jo < n) rb[jo] = make_int2(collh, collf);
+        __syncthreads();
       }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
+    for (int T = kSkew * w + my_rounds * C2; T < T_total; ++T) __syncthreads();
+
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) best = imax(best, __shfl_xor(best, off, 64));
-    if (lane == 0) a.out[sid] = best;
+    if (lane == 0) lbest[w] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int b = lbest[0];
+#pragma unroll
+      for (int x = 1; x < W2; ++x) b = imax(b, lbest[x]);
+      a.out[sid] = b;
+    }
+    __syncthreads();
   }
 }
 
-template <int R>
-hipError_t launch_r(int grid, const IntraArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_intra_i32<R>), dim3(grid), dim3(64), intra_lds_bytes(R), s, a);
+template <int R, int W2>
+hipError_t launch_rw(int grid, const IntraArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_intra_i32<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-int intra_lds_bytes(int R) { return kIntraCodes * 64 * R * (int)sizeof(int16_t); }
-
-hipError_t launch_intra(int R, int grid, const IntraArgs& a, hipStream_t s) {
+hipError_t launch_intra(int R, int W2, int grid, const IntraArgs& a, hipStream_t s) {
   if (grid <= 0) return hipSuccess;
-  if (R == 2) return launch_r<2>(grid, a, s);
-  if (R == 4) return launch_r<4>(grid, a, s);
-  if (R == 8) return launch_r<8>(grid, a, s);
+#define SWDB_CASE(r, w) \
+  if (R == r && W2 == w) return launch_rw<r, w>(grid, a, s);
+  SWDB_CASE(2, 1) SWDB_CASE(4, 1) SWDB_CASE(8, 1)
+  SWDB_CASE(2, 2) SWDB_CASE(4, 2) SWDB_CASE(8, 2)
+  SWDB_CASE(2, 4) SWDB_CASE(4, 4) SWDB_CASE(8, 4)
+  SWDB_CASE(2, 8) SWDB_CASE(4, 8) SWDB_CASE(8, 8)
+#undef SWDB_CASE
   return hipErrorInvalidValue;
 }
 

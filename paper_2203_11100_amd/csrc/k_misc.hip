@@ -5,12 +5,12 @@ namespace swdb {
 namespace {
 
 // Builds both query profiles from the query codes and the substitution
-// matrix: the inter-task layout [row][26] (codes 0..23, pad, spare) and the
-// intra-task layout [25][m_pad2] (codes 0..23, pad).  Entry (i, c) is
+// matrix: the inter-task layout [row][26] int16 (codes 0..23, pad, spare) and
+// the intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
 // S(a_i, c); rows past the query end and the pad/spare codes get kPadScore.
 // Thread 0 also clears the rescoring list's count.
 __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
-                          uint16_t* __restrict__ prof, int m_pad, int16_t* __restrict__ prof2,
+                          uint16_t* __restrict__ prof, int m_pad, int8_t* __restrict__ prof2,
                           int m_pad2, int32_t* __restrict__ flag_count) {
   const int64_t n1 = (int64_t)m_pad * kProfRowShorts;
   const int64_t n2 = (int64_t)kIntraCodes * m_pad2;
@@ -27,7 +27,7 @@ __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
       v = qc < SW_ALPHA ? (int)mat.v[qc * SW_ALPHA + c] : kPadScore;
     }
     if (idx < n1) prof[idx] = (uint16_t)(int16_t)v;
-    else prof2[idx - n1] = (int16_t)v;
+    else prof2[idx - n1] = (int8_t)v;
   }
 }
 
@@ -39,7 +39,7 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
 }  // namespace
 
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
-                          int m_pad, int16_t* prof2, int m_pad2, int32_t* flag_count,
+                          int m_pad, int8_t* prof2, int m_pad2, int32_t* flag_count,
                           hipStream_t s) {
   const int64_t total = (int64_t)m_pad * kProfRowShorts + (int64_t)kIntraCodes * m_pad2;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 2048);

@@ -88,7 +88,7 @@ struct sw_db {
 
   // per-query buffers, grown on demand
   swdb::DevBuf<uint32_t> prof;
-  swdb::DevBuf<int16_t> prof2;
+  swdb::DevBuf<int8_t> prof2;
   swdb::DevBuf<uint8_t> q_stage;
   swdb::DevBuf<int32_t> out_stage;
 
@@ -104,7 +104,7 @@ struct sw_db {
   // options
   bool timing = false;
   int32_t sat_limit = 32767;
-  int32_t opt_rows = 0, opt_waves = 0, opt_intra_rows = 0;
+  int32_t opt_rows = 0, opt_waves = 0, opt_intra_rows = 0, opt_intra_waves = 0;
 
   // bookkeeping since the last sw_get_stats
   sw_stats stats{};
@@ -153,17 +153,34 @@ int pick_rows(const sw_db* db, int m) {
 }
 
 int pick_waves(const sw_db* db, int n_strips) {
-  if (db->opt_waves) return std::min(db->opt_waves, 8);
-  int w = 4;
-  while (w > 1 && n_strips < w) w >>= 1;
-  return w;
+  if (db->opt_waves) return db->opt_waves;
+  // more waves per bin shortens each bin's strip pipeline; measured best at 8
+  // even when some waves idle in the last round
+  (void)n_strips;
+  return 8;
 }
 
-int pick_intra_rows(const sw_db* db, int m) {
-  if (db->opt_intra_rows) return db->opt_intra_rows;
-  if (m <= 128) return 2;
-  if (m <= 256) return 4;
-  return 8;
+// Rows per lane (R) and waves (W2) of the intra-task kernel for a query of
+// length m: the smallest estimated latency for one long sequence, where a
+// pass of 64R rows costs about (10R + 10) VALU ops per step, waves beyond one
+// per SIMD share it, and the passes run in rounds of W2.
+void pick_intra(const sw_db* db, int m, int max_waves, int* R_out, int* W2_out) {
+  double best = 1e300;
+  int bR = 8, bW = 1;
+  for (int R : {2, 4, 8}) {
+    if (db->opt_intra_rows && R != db->opt_intra_rows) continue;
+    const int passes = (m + 64 * R - 1) / (64 * R);
+    for (int W2 : {1, 2, 4, 8}) {
+      if (W2 > max_waves) continue;
+      if (db->opt_intra_waves && max_waves > 2 && W2 != db->opt_intra_waves) continue;
+      const int rounds = (passes + W2 - 1) / W2;
+      const double share = W2 > 4 ? W2 / 4.0 : 1.0;
+      const double est = rounds * (10.0 * R + 10.0) * share + 1e-3 * W2;
+      if (est < best) { best = est; bR = R; bW = W2; }
+    }
+  }
+  *R_out = bR;
+  *W2_out = bW;
 }
 
 enum TimedKind { kTimeTotal = 0, kTimeInter = 1, kTimeIntra = 2, kTimeRescore = 3 };
@@ -208,10 +225,12 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   const int m_pad = (m + R - 1) / R * R;
   const int n_strips = m_pad / R;
   const int W = pick_waves(db, n_strips);
-  const int RR = pick_intra_rows(db, m);
-  const int rows2 = 64 * RR;
+  int RR = 8, W2 = 1, RRr = 8, W2r = 1;
+  pick_intra(db, m, 8, &RR, &W2);     // long sequences
+  pick_intra(db, m, 2, &RRr, &W2r);   // rescoring (usually empty)
+  // one intra-task profile serves both launches: pad to the larger pass
+  const int rows2 = 64 * std::max(RR, RRr);
   const int m_pad2 = (m + rows2 - 1) / rows2 * rows2;
-  const int n_pass = m_pad2 / rows2;
 
   if ((e = db->prof.reserve((size_t)m_pad * kProfRowDwords)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
@@ -230,7 +249,6 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   ia.offs = db->offs.p;
   ia.prof2 = db->prof2.p;
   ia.m_pad2 = m_pad2;
-  ia.n_pass = n_pass;
   ia.go = go;
   ia.ge = ge;
   ia.out = d_out;
@@ -245,9 +263,10 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
     la.count = (int32_t)n_long;
     la.scratch = db->rb_long.p;
     la.scratch_stride = std::max<int64_t>(db->plan.max_long_len, 1);
+    la.n_pass = (m + 64 * RR - 1) / (64 * RR);
     const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
-    if ((e = launch_intra(RR, grid, la, db->aux_stream)) != hipSuccess)
+    if ((e = launch_intra(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
     time_end(db, tl, db->aux_stream);
     if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
@@ -284,8 +303,9 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
     ra.count = 0;
     ra.scratch = db->rb_resc.p;
     ra.scratch_stride = std::max<int64_t>(db->plan.max_bin_len, 1);
+    ra.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
     const int tr = time_begin(db, kTimeRescore, s);
-    if ((e = launch_intra(RR, kIntraGridRescore, ra, s)) != hipSuccess)
+    if ((e = launch_intra(RRr, W2r, kIntraGridRescore, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
     time_end(db, tr, s);
   }
@@ -568,6 +588,11 @@ int sw_set_option(sw_db* db, int32_t key, int64_t value) {
       if (value != 0 && value != 2 && value != 4 && value != 8)
         return fail(SW_EINVAL, "intra rows must be 0, 2, 4 or 8");
       db->opt_intra_rows = (int32_t)value;
+      return SW_OK;
+    case SW_OPT_INTRA_WAVES:
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
+        return fail(SW_EINVAL, "intra waves must be 0, 1, 2, 4 or 8");
+      db->opt_intra_waves = (int32_t)value;
       return SW_OK;
     default:
       return fail(SW_EINVAL, "unknown option " + std::to_string(key));

@@ -78,14 +78,16 @@ def test_strip_and_wave_options(sw, rows, waves):
 
 
 @pytest.mark.parametrize("intra_rows", [2, 4, 8])
+@pytest.mark.parametrize("intra_waves", [1, 2, 4, 8])
 @pytest.mark.parametrize("t_long", [1, 100])
-def test_intra_task_path(sw, intra_rows, t_long):
+def test_intra_task_path(sw, intra_rows, intra_waves, t_long):
     res, offs = _ragged_db(2)
-    q = swinputs.random_residues(700, np.random.default_rng(6))
-    say("t_long=%d intra_rows=%d" % (t_long, intra_rows))
+    q = swinputs.random_residues(1700, np.random.default_rng(6))
+    say("t_long=%d intra_rows=%d intra_waves=%d" % (t_long, intra_rows, intra_waves))
     with sw.Database(res, offs, long_threshold=t_long) as db:
         assert db.info()["n_long"] > 0
         db.set_option(sw.SW_OPT_INTRA_ROWS, intra_rows)
+        db.set_option(sw.SW_OPT_INTRA_WAVES, intra_waves)
         got = db.search(q, B62, 10, 2)
     assert (got == _oracle(q, res, offs)).all()
 
