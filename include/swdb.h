@@ -85,7 +85,7 @@ typedef struct sw_db sw_db;
  * this many residues use the intra-task kernel (<= 0 selects the default,
  * SW_DEFAULT_LONG_THRESHOLD).
  */
-#define SW_DEFAULT_LONG_THRESHOLD 3072
+#define SW_DEFAULT_LONG_THRESHOLD 2048
 int sw_db_load(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
                sw_db** out_db);
 int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,

@@ -21,9 +21,11 @@ struct Matrix {
   int8_t v[SW_ALPHA * SW_ALPHA];
 };
 
-// Inter-task profile: one row of 26 int16 per query position (codes 0..23,
-// the pad code 24, one spare), i.e. 13 dwords per row.
-constexpr int kProfRowShorts = 26;
+// Inter-task profile: for each pair of query rows (2r, 2r+1), 26 dwords
+// (codes 0..23, the pad code 24, one spare); dword (r, c) = score of row 2r
+// against code c in bits 0..15, of row 2r+1 in bits 16..31.  13 dwords per
+// query row.
+constexpr int kProfPairDwords = 26;
 constexpr int kProfRowDwords = 13;
 // Score given to padding (pad code, and query rows past the end).  Any value
 // <= 0 keeps padded cells from raising a maximum.

@@ -34,11 +34,12 @@
 // Splitting one bin's strips over W waves divides its latency by W, which
 // keeps the longest bins from trailing the rest of the grid.
 //
-// The query profile rows of the current strip are staged in LDS, one row of
-// 26 int16 per query position ([row][residue code]).  All lanes read the same
-// row at once, so the addresses fall in 13 consecutive dwords: no bank
-// conflicts.  The two halves' scores are fetched with two 16-bit LDS reads
-// and packed into one register.
+// The query profile rows of the current strip are staged in LDS as row pairs:
+// dword (r, c) holds the scores of query rows 2r and 2r+1 against residue
+// code c (26 codes: 24 residues, pad, spare).  All lanes read the same row
+// pair at once, so the addresses fall in 26 consecutive dwords: no bank
+// conflicts.  One read per row pair and half (lo/hi sequence) yields two
+// rows; one byte permute per row packs the lo and hi sequences' scores.
 #include "internal.h"
 
 namespace swdb {
@@ -123,7 +124,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
 #pragma unroll
     for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
     uint32_t hdiag = 0;
-    const unsigned short* slot = reinterpret_cast<const unsigned short*>(&lprof[w][q & 1][0]);
+    const uint32_t* slot = &lprof[w][q & 1][0];
     const bool more = q + 1 < my_rounds;
     for (int c = 0; c < C; ++c) {
       const uint2 rr = rr_n;
@@ -143,14 +144,18 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
       uint32_t out_h[4], out_f[4];
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
-        // two 16-bit LDS reads per row, packed into one register (16-bit
-        // loads on gfx950 zero the other half, so the packing costs one op)
-        const unsigned short* plo = slot + ((rr.x >> (8 * jj)) & 0xffu);
-        const unsigned short* phi = slot + ((rr.y >> (8 * jj)) & 0xffu);
+        // one 32-bit LDS read per row pair and code gives two rows' scores;
+        // the lo and hi sequences' reads are interleaved into packed pairs
+        const uint32_t* plo = slot + ((rr.x >> (8 * jj)) & 0xffu);
+        const uint32_t* phi = slot + ((rr.y >> (8 * jj)) & 0xffu);
         uint32_t p[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k)
-          p[k] = (uint32_t)plo[k * kProfRowShorts] | ((uint32_t)phi[k * kProfRowShorts] << 16);
+        for (int k2 = 0; k2 < R / 2; ++k2) {
+          const uint32_t A = plo[k2 * kProfPairDwords], B = phi[k2 * kProfPairDwords];
+          // v_perm_b32: bytes {A0, A1, B0, B1} and {A2, A3, B2, B3}
+          p[2 * k2] = __builtin_amdgcn_perm(B, A, 0x05040100u);
+          p[2 * k2 + 1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+        }
         uint32_t hd = hdiag;
         hdiag = up_h[jj];
         uint32_t F = up_f[jj];

@@ -4,30 +4,37 @@
 namespace swdb {
 namespace {
 
+__device__ __forceinline__ int profile_score(const uint8_t* __restrict__ q, int m,
+                                             const Matrix& mat, int i, int c) {
+  if (i >= m || c >= SW_ALPHA) return kPadScore;
+  const int qc = q[i];
+  return qc < SW_ALPHA ? (int)mat.v[qc * SW_ALPHA + c] : kPadScore;
+}
+
 // Builds both query profiles from the query codes and the substitution
-// matrix: the inter-task layout [row][26] int16 (codes 0..23, pad, spare) and
-// the intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
+// matrix: the inter-task row-pair layout (see kProfPairDwords) and the
+// intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
 // S(a_i, c); rows past the query end and the pad/spare codes get kPadScore.
 // Thread 0 also clears the rescoring list's count.
 __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
-                          uint16_t* __restrict__ prof, int m_pad, int8_t* __restrict__ prof2,
+                          uint32_t* __restrict__ prof, int m_pad, int8_t* __restrict__ prof2,
                           int m_pad2, int32_t* __restrict__ flag_count) {
-  const int64_t n1 = (int64_t)m_pad * kProfRowShorts;
+  const int64_t n1 = (int64_t)(m_pad / 2) * kProfPairDwords;
   const int64_t n2 = (int64_t)kIntraCodes * m_pad2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx == 0 && flag_count) *flag_count = 0;
   for (; idx < n1 + n2; idx += stride) {
-    int i, c;
-    if (idx < n1) { i = (int)(idx / kProfRowShorts); c = (int)(idx % kProfRowShorts); }
-    else { c = (int)((idx - n1) / m_pad2); i = (int)((idx - n1) % m_pad2); }
-    int v = kPadScore;
-    if (i < m && c < SW_ALPHA) {
-      const int qc = q[i];
-      v = qc < SW_ALPHA ? (int)mat.v[qc * SW_ALPHA + c] : kPadScore;
+    if (idx < n1) {
+      const int r = (int)(idx / kProfPairDwords), c = (int)(idx % kProfPairDwords);
+      const uint32_t lo = (uint16_t)(int16_t)profile_score(q, m, mat, 2 * r, c);
+      const uint32_t hi = (uint16_t)(int16_t)profile_score(q, m, mat, 2 * r + 1, c);
+      prof[idx] = lo | (hi << 16);
+    } else {
+      const int64_t j = idx - n1;
+      const int c = (int)(j / m_pad2), i = (int)(j % m_pad2);
+      prof2[j] = (int8_t)profile_score(q, m, mat, i, c);
     }
-    if (idx < n1) prof[idx] = (uint16_t)(int16_t)v;
-    else prof2[idx - n1] = (int8_t)v;
   }
 }
 
@@ -41,11 +48,11 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
                           int m_pad, int8_t* prof2, int m_pad2, int32_t* flag_count,
                           hipStream_t s) {
-  const int64_t total = (int64_t)m_pad * kProfRowShorts + (int64_t)kIntraCodes * m_pad2;
+  const int64_t total = (int64_t)(m_pad / 2) * kProfPairDwords + (int64_t)kIntraCodes * m_pad2;
   int grid = (int)std::min<int64_t>((total + 255) / 256, 2048);
   if (grid < 1) grid = 1;
-  hipLaunchKernelGGL(k_profile, dim3(grid), dim3(256), 0, s, d_query, m, mat,
-                     reinterpret_cast<uint16_t*>(prof), m_pad, prof2, m_pad2, flag_count);
+  hipLaunchKernelGGL(k_profile, dim3(grid), dim3(256), 0, s, d_query, m, mat, prof, m_pad, prof2,
+                     m_pad2, flag_count);
   return hipGetLastError();
 }
 
