@@ -120,7 +120,12 @@ int sw_search_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
                     const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
                     int32_t* d_out_scores, void* hip_stream);
 
-/* sw_search_batch: many queries against the resident database.
+/* sw_search_batch: many queries against the resident database in one
+ * persistent launch.  Queries are sorted by length and paired, two queries
+ * per 32-bit register lane; the work list of (query pair, half bin) items is
+ * drained costliest first by a fixed grid of workgroups.  Repeating a batch
+ * with the same query lengths, matrix, gaps and buffers replays a captured
+ * HIP graph.
  *   queries       : host, concatenated codes, query q is
  *                   queries[query_offsets[q] .. query_offsets[q+1]).
  *   query_offsets : host, int64_t[n_queries + 1].
@@ -148,7 +153,9 @@ enum sw_option {
   SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto), 16, 32 */
   SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8 */
   SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
-  SW_OPT_INTRA_WAVES = 6  /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
+  SW_OPT_INTRA_WAVES = 6, /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
+  SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph
+                             (default 1; graphs are not used while TIMING is on) */
 };
 int sw_set_option(sw_db* db, int32_t key, int64_t value);
 

@@ -15,11 +15,11 @@ import numpy as np
 from . import _native
 from ._native import (SwError, SW_ALPHA, SW_BIN_SEQS, SW_PAD_CODE, SW_MIN_BIN_LEN,
                       SW_DEFAULT_LONG_THRESHOLD, SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS,
-                      SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES)
+                      SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES, SW_OPT_GRAPHS)
 
 __all__ = ["Database", "SwError", "plan", "pack", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
            "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
-           "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES"]
+           "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS"]
 
 
 def _ptr(a) -> Optional[int]:

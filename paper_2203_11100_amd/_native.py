@@ -21,6 +21,7 @@ SW_MIN_BIN_LEN = 64
 SW_DEFAULT_LONG_THRESHOLD = 2048
 SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 1, 2, 3, 4, 5
 SW_OPT_INTRA_WAVES = 6
+SW_OPT_GRAPHS = 7
 
 _STATUS_NAMES = {1: "SW_EINVAL", 2: "SW_ERANGE", 3: "SW_ENOMEM", 4: "SW_EDEVICE", 5: "SW_EBUSY"}
 

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswdb.so")
-SOURCES = ["layout.cpp", "runtime.hip", "k_inter.hip", "k_intra.hip", "k_misc.hip"]
+SOURCES = ["layout.cpp", "runtime.hip", "k_inter.hip", "k_batch.hip", "k_intra.hip", "k_misc.hip"]
 ARCH = os.environ.get("SWDB_OFFLOAD_ARCH", "gfx950")
 
 

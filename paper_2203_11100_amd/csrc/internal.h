@@ -43,24 +43,62 @@ struct InterArgs {
   uint4* rb;                  // boundary-row buffers of all bins
   const int32_t* slot_seq;
   int32_t* out;
-  int32_t* flag_count;        // rescoring list: count, then sequence ids
-  int32_t* flag_list;
+  int32_t* flag_count;        // rescoring list: count, then {sid, query}
+  int2* flag_list;
   int32_t sat_limit;
+};
+
+// Per-query parameters of the intra-task kernel.
+struct QueryDesc {
+  int64_t prof2_off;          // byte offset of the query's [25][m_pad2] int8 profile
+  int64_t out_off;            // offset of the query's score row in `out`
+  int32_t m_pad2;             // profile row length: a multiple of 64*R
+  int32_t n_pass;             // passes of 64*R rows covering the query
 };
 
 struct IntraArgs {
   const uint8_t* res;         // contiguous residues, original order
   const int64_t* offs;
-  const int32_t* items;       // sequence ids to score
+  const int2* items;          // {sequence id, query index}
   const int32_t* count_ptr;   // device item count (rescoring) or nullptr
   int32_t count;              // host item count when count_ptr == nullptr
-  const int8_t* prof2;        // [25][m_pad2] int8
-  int32_t m_pad2;             // multiple of 64*R for every R used with it
-  int32_t n_pass;             // passes of 64*R rows covering the query
+  const int8_t* prof2;        // intra-task profiles of all queries
+  QueryDesc q0;               // the query when `queries` is nullptr
+  const QueryDesc* queries;   // per-query parameters (batched), or nullptr
   int32_t go, ge;
   int2* scratch;              // per-workgroup boundary rows
   int64_t scratch_stride;     // int2 elements per workgroup
   int32_t* out;
+};
+
+// Batched inter-task kernel: the two 16-bit halves of a lane hold two
+// queries (a pair) against one database sequence.
+constexpr int kBatchRowDwords = 26;   // dword (i, c) = (S(a_i, c), S(b_i, c))
+
+struct PairDesc {
+  int64_t prof_off;           // dword offset of the pair's [rows][26] profile
+  int32_t n_strips;           // strips of R rows covering the longer query
+  int32_t qa, qb;             // query indices (qb < 0: high half unused)
+  int32_t pad_;
+};
+
+struct BatchArgs {
+  const uint32_t* res;        // interleaved store (dwords)
+  const BinDesc* bins;
+  const int2* items;          // {pair, 2 * bin + half}, costliest first
+  int32_t n_items;
+  int32_t* counter;           // work-queue head, zero at launch
+  const PairDesc* pairs;
+  const uint32_t* prof;
+  uint32_t go2, ge2;
+  uint4* rb;                  // per-workgroup boundary rows
+  int64_t rb_stride;          // uint4 per workgroup
+  const int32_t* slot_seq;
+  int32_t* out;               // [n_queries][n_seqs]
+  int64_t n_seqs;
+  int32_t* flag_count;        // rescoring list: count, then {sid, query}
+  int2* flag_list;
+  int32_t sat_limit;
 };
 
 // Kernel launchers (return hipSuccess or the launch error).
@@ -70,5 +108,13 @@ hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_t s);
 hipError_t launch_intra(int RR, int W2, int grid, const IntraArgs& a, hipStream_t s);
+hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t s);
+int batch_workgroups_per_cu(int R, int W);
+// Pair profiles for `n_pairs` pairs and intra-task profiles for `n_queries`
+// queries of a batch (see k_misc.hip for the layouts).
+hipError_t launch_batch_profiles(const uint8_t* d_queries, const int64_t* d_qoffs, int n_queries,
+                                 const Matrix& mat, const PairDesc* d_pairs, int n_pairs, int R,
+                                 int64_t max_work, uint32_t* prof, const QueryDesc* d_qdesc,
+                                 int8_t* prof2, hipStream_t s);
 
 }  // namespace swdb

@@ -1,0 +1,195 @@
+// Batched inter-task Smith-Waterman/Gotoh kernel: many queries against the
+// resident database in one persistent launch (paper section 2.2, database
+// search; section 4.1 runs 20 queries against one database).
+//
+// Queries are sorted by length and paired; the two 16-bit halves of every
+// register hold the two queries of a pair, scored against the same database
+// sequence, so each lane owns one sequence and a wave 64.  The profile of a
+// pair stores, for query row i and residue code c, the dword
+// (S(a_i, c), S(b_i, c)): one 32-bit LDS read per row returns both halves'
+// scores with no packing op, and all lanes read the same 26-dword row, so the
+// reads never conflict on banks.  The cell arithmetic, the R-row strips, the
+// W-wave strip pipeline and the boundary-row handling are those of the
+// single-query inter-task kernel (k_inter.hip).
+//
+// Work is a list of (pair, half bin) items, costliest first; a half bin is
+// the 64 even or odd slots of a 128-sequence bin of the interleaved store.
+// Each workgroup takes items from a device counter until the list is
+// exhausted (every workgroup reaches the exit test after each item), and
+// keeps one boundary-row buffer of its own for the item it is working on.
+#include "internal.h"
+#include "packed16.h"
+
+namespace swdb {
+namespace {
+
+template <int R, int W>
+__global__ __launch_bounds__(64 * W) void k_batch_i16(BatchArgs a) {
+  constexpr int D = 2;   // superstep skew between consecutive waves
+  constexpr int kSlot = R * kBatchRowDwords;
+  constexpr int kStage = (kSlot + 63) / 64;
+  __shared__ uint32_t lprof[W][2][kSlot];
+  __shared__ uint32_t lbest[W][64];
+  __shared__ int litem;
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint4* __restrict__ rbb = a.rb + (size_t)blockIdx.x * a.rb_stride;
+  const uint32_t go = a.go2, ge = a.ge2;
+
+  for (;;) {
+    if (threadIdx.x == 0) litem = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(litem);
+    __syncthreads();
+    if (it >= a.n_items) break;
+
+    const int2 iv = a.items[it];
+    const PairDesc pd = a.pairs[iv.x];
+    const BinDesc bin = a.bins[iv.y >> 1];
+    const int half = iv.y & 1;
+    const int C = (int)(bin.len >> 2);
+    const int S = pd.n_strips;
+    const int q_last = (S - 1) / W, w_last = (S - 1) % W;
+    const int T_total = q_last * C + D * w_last + C;
+    const int my_rounds = (w < S) ? (S - 1 - w) / W + 1 : 0;
+    const uint32_t* __restrict__ prof = a.prof + pd.prof_off;
+    // lane's residues: dword res_off + c*128 + 2*lane + half
+    const uint32_t* __restrict__ rlane = a.res + bin.res_off + 2 * lane + half;
+
+    if (my_rounds > 0) {
+      const uint32_t* src = prof + (size_t)w * kSlot;
+#pragma unroll
+      for (int x = 0; x < kStage; ++x)
+        if (x * 64 + lane < kSlot) lprof[w][0][x * 64 + lane] = src[x * 64 + lane];
+    }
+    __syncthreads();
+
+    uint32_t rr_n = 0;
+    uint4 b_n = make_uint4(0, 0, 0, 0), b_n2 = make_uint4(0, 0, 0, 0);
+    auto fetch = [&](int s, int c) {
+      rr_n = rlane[(size_t)c * SW_BIN_SEQS];
+      if (s > 0) {
+        const uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
+        b_n = p[0];
+        b_n2 = p[1];
+      } else {
+        b_n = make_uint4(0, 0, 0, 0);
+        b_n2 = make_uint4(0, 0, 0, 0);
+      }
+    };
+
+    uint32_t H[R], E[R];
+    uint32_t best = 0;
+    if (w == 0 && my_rounds > 0) fetch(0, 0);
+    for (int T = 0; T < D * w; ++T) {
+      if (T == D * w - 1 && my_rounds > 0) fetch(w, 0);
+      __syncthreads();
+    }
+    for (int q = 0; q < my_rounds; ++q) {
+      const int s = q * W + w;
+#pragma unroll
+      for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
+      uint32_t hdiag = 0;
+      const uint32_t* slot = &lprof[w][q & 1][0];
+      const bool more = q + 1 < my_rounds;
+      for (int c = 0; c < C; ++c) {
+        const uint32_t rr = rr_n;
+        const uint32_t up_h[4] = {b_n.x, b_n.z, b_n2.x, b_n2.z};
+        const uint32_t up_f[4] = {b_n.y, b_n.w, b_n2.y, b_n2.w};
+        if (c + 1 < C) fetch(s, c + 1);
+        else if (more) fetch(s + W, 0);
+        const bool stage = more && c == C - 1;
+        uint32_t st[kStage];
+        if (stage) {
+          const uint32_t* src = prof + (size_t)(s + W) * kSlot;
+#pragma unroll
+          for (int x = 0; x < kStage; ++x)
+            if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
+        }
+        uint32_t out_h[4], out_f[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const uint32_t* pc = slot + ((rr >> (8 * jj)) & 0xffu);
+          uint32_t hd = hdiag;
+          hdiag = up_h[jj];
+          uint32_t F = up_f[jj];
+#pragma unroll
+          for (int k = 0; k < R; ++k) cell(hd, H[k], E[k], F, best, pc[k * kBatchRowDwords], go, ge);
+          out_h[jj] = H[R - 1];
+          out_f[jj] = F;
+        }
+        if (s < S - 1) {
+          uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
+          p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
+          p[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+        }
+        if (stage) {
+#pragma unroll
+          for (int x = 0; x < kStage; ++x)
+            if (x * 64 + lane < kSlot) lprof[w][(q + 1) & 1][x * 64 + lane] = st[x];
+        }
+        __syncthreads();
+      }
+    }
+    for (int T = D * w + my_rounds * C; T < T_total; ++T) __syncthreads();
+
+    lbest[w][lane] = best;
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int x = 1; x < W; ++x) best = vmax(best, lbest[x][lane]);
+      const int sid = a.slot_seq[bin.slot0 + 2 * lane + half];
+      if (sid >= 0) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+          const int qi = hh ? pd.qb : pd.qa;
+          if (qi < 0) continue;
+          const int score = (int)((best >> (16 * hh)) & 0xffffu);
+          if (score >= a.sat_limit) {
+            const int idx = atomicAdd(a.flag_count, 1);
+            a.flag_list[idx] = make_int2(sid, qi);
+          } else {
+            a.out[(size_t)qi * a.n_seqs + sid] = score;
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int R, int W>
+hipError_t launch_rw(int grid, const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_i16<R, W>), dim3(grid), dim3(64 * W), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int R, int W>
+int occupancy() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_batch_i16<R, W>),
+                                                   64 * W, 0) != hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+}  // namespace
+
+hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define SWDB_CASE(r, w) \
+  if (R == r && W == w) return launch_rw<r, w>(grid, a, s);
+  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+#undef SWDB_CASE
+  return hipErrorInvalidValue;
+}
+
+int batch_workgroups_per_cu(int R, int W) {
+#define SWDB_CASE(r, w) \
+  if (R == r && W == w) return occupancy<r, w>();
+  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+#undef SWDB_CASE
+  return 1;
+}
+
+}  // namespace swdb

@@ -41,26 +41,10 @@
 // conflicts.  One read per row pair and half (lo/hi sequence) yields two
 // rows; one byte permute per row packs the lo and hi sequences' scores.
 #include "internal.h"
+#include "packed16.h"
 
 namespace swdb {
 namespace {
-
-typedef short s16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ uint32_t add_sat(uint32_t a, uint32_t b) {
-  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(
-                                          __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
-}
-// per 16-bit half: max(a - b, 0) for a, b read as unsigned
-__device__ __forceinline__ uint32_t sub_floor(uint32_t a, uint32_t b) {
-  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
-                                          __builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
-}
-__device__ __forceinline__ uint32_t vmax(uint32_t a, uint32_t b) {
-  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(
-                                          __builtin_bit_cast(s16x2, a), __builtin_bit_cast(s16x2, b)));
-}
 
 template <int R, int W>
 __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
@@ -82,7 +66,8 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
   if (my_rounds > 0) {
     const uint32_t* src = a.prof + (size_t)w * kSlot;
 #pragma unroll
-    for (int x = lane; x < kSlot; x += 64) lprof[w][0][x] = src[x];
+    for (int x = 0; x < kStage; ++x)
+      if (x * 64 + lane < kSlot) lprof[w][0][x * 64 + lane] = src[x * 64 + lane];
   }
   __syncthreads();
 
@@ -160,15 +145,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
         hdiag = up_h[jj];
         uint32_t F = up_f[jj];
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          uint32_t h = vmax(vmax(add_sat(hd, p[k]), E[k]), F);
-          hd = H[k];
-          H[k] = h;
-          best = vmax(best, h);
-          const uint32_t t = sub_floor(h, go);
-          E[k] = vmax(sub_floor(E[k], ge), t);
-          F = vmax(sub_floor(F, ge), t);
-        }
+        for (int k = 0; k < R; ++k) cell(hd, H[k], E[k], F, best, p[k], go, ge);
         out_h[jj] = H[R - 1];
         out_f[jj] = F;
       }
@@ -200,7 +177,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
     const int score = (int)((best >> (16 * half)) & 0xffffu);
     if (score >= a.sat_limit) {
       const int idx = atomicAdd(a.flag_count, 1);
-      a.flag_list[idx] = sid;
+      a.flag_list[idx] = make_int2(sid, 0);
     } else {
       a.out[sid] = score;
     }

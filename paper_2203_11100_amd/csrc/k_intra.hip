@@ -4,7 +4,8 @@
 // border elements; section 2.3: SW#db switches to it by sequence length).
 //
 // One workgroup of W2 waves scores one (query, database sequence) pair at a
-// time.  The query is cut into passes of 64*R rows; lane l of a wave owns R
+// time, taking pairs from an item list (one query, or every query of a
+// batch with per-query profile offsets).  The query is cut into passes of 64*R rows; lane l of a wave owns R
 // consecutive rows of its pass and the wave sweeps the database sequence as
 // an anti-diagonal wavefront: at step t lane l computes column j = t - l of
 // its rows, so it receives the H and F values of row (top - 1) for column j
@@ -100,12 +101,15 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
   const int count = a.count_ptr ? *a.count_ptr : a.count;
   int2* __restrict__ rb = a.scratch + (size_t)blockIdx.x * a.scratch_stride;
   const int go = a.go, ge = a.ge;
-  const int P = a.n_pass;
-  const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
-  const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
 
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
-    const int sid = a.items[it];
+    const int2 item = a.items[it];
+    const int sid = item.x;
+    const QueryDesc qd = a.queries ? a.queries[item.y] : a.q0;
+    const int P = qd.n_pass;
+    const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
+    const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
+    const int8_t* __restrict__ qprof = a.prof2 + qd.prof2_off;
     const int64_t b0 = a.offs[sid];
     const int n = (int)(a.offs[sid + 1] - b0);
     const uint8_t* __restrict__ bseq = a.res + b0;
@@ -138,10 +142,10 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
       const bool more = q + 1 < my_rounds;
       const bool last_pass = p == P - 1;
       {  // stage this pass's profile rows (read back only by this wave)
-        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.prof2);
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(qprof);
         uint4* dst = reinterpret_cast<uint4*>(lprof);
         constexpr int per_code = ROWS / 16;           // uint4 per code row
-        const int src_stride = a.m_pad2 / 16;
+        const int src_stride = qd.m_pad2 / 16;
         for (int x = lane; x < kIntraCodes * per_code; x += 64) {
           const int code = x / per_code, r = x - code * per_code;
           dst[x] = src[(size_t)code * src_stride + (size_t)p * per_code + r];
@@ -203,7 +207,7 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
       int b = lbest[0];
 #pragma unroll
       for (int x = 1; x < W2; ++x) b = imax(b, lbest[x]);
-      a.out[sid] = b;
+      a.out[qd.out_off + sid] = b;
     }
     __syncthreads();
   }

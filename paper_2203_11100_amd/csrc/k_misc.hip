@@ -38,6 +38,44 @@ __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
   }
 }
 
+// Pair profiles and intra-task profiles of a batch.  blockIdx.y < n_pairs
+// selects a pair: dword (i, c) of its [n_strips*R rows][26] profile holds
+// (S(a_i, c), S(b_i, c)) with kPadScore past either query's end.  Larger
+// blockIdx.y select a query's intra-task [25][m_pad2] int8 profile.
+__global__ void k_batch_profiles(const uint8_t* __restrict__ queries,
+                                 const int64_t* __restrict__ qoffs, Matrix mat,
+                                 const PairDesc* __restrict__ pairs, int n_pairs, int R,
+                                 uint32_t* __restrict__ prof,
+                                 const QueryDesc* __restrict__ qdesc, int8_t* __restrict__ prof2) {
+  const int y = blockIdx.y;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (y < n_pairs) {
+    const PairDesc pd = pairs[y];
+    const int64_t total = (int64_t)pd.n_strips * R * kBatchRowDwords;
+    const uint8_t* qa = queries + qoffs[pd.qa];
+    const int ma = (int)(qoffs[pd.qa + 1] - qoffs[pd.qa]);
+    const uint8_t* qb = pd.qb >= 0 ? queries + qoffs[pd.qb] : nullptr;
+    const int mb = pd.qb >= 0 ? (int)(qoffs[pd.qb + 1] - qoffs[pd.qb]) : 0;
+    for (int64_t idx = start; idx < total; idx += stride) {
+      const int i = (int)(idx / kBatchRowDwords), c = (int)(idx % kBatchRowDwords);
+      const uint32_t lo = (uint16_t)(int16_t)profile_score(qa, ma, mat, i, c);
+      const uint32_t hi = (uint16_t)(int16_t)profile_score(qb, mb, mat, i, c);
+      prof[pd.prof_off + idx] = lo | (hi << 16);
+    }
+  } else {
+    const int qi = y - n_pairs;
+    const QueryDesc qd = qdesc[qi];
+    const uint8_t* q = queries + qoffs[qi];
+    const int m = (int)(qoffs[qi + 1] - qoffs[qi]);
+    const int64_t total = (int64_t)kIntraCodes * qd.m_pad2;
+    for (int64_t idx = start; idx < total; idx += stride) {
+      const int c = (int)(idx / qd.m_pad2), i = (int)(idx % qd.m_pad2);
+      prof2[qd.prof2_off + idx] = (int8_t)profile_score(q, m, mat, i, c);
+    }
+  }
+}
+
 __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -53,6 +91,19 @@ hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_profile, dim3(grid), dim3(256), 0, s, d_query, m, mat, prof, m_pad, prof2,
                      m_pad2, flag_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_profiles(const uint8_t* d_queries, const int64_t* d_qoffs, int n_queries,
+                                 const Matrix& mat, const PairDesc* d_pairs, int n_pairs, int R,
+                                 int64_t max_work, uint32_t* prof, const QueryDesc* d_qdesc,
+                                 int8_t* prof2, hipStream_t s) {
+  const int ys = n_pairs + n_queries;
+  if (ys <= 0) return hipSuccess;
+  if (ys > 65535) return hipErrorInvalidValue;
+  const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((max_work + 255) / 256, 256));
+  hipLaunchKernelGGL(k_batch_profiles, dim3(gx, ys), dim3(256), 0, s, d_queries, d_qoffs, mat,
+                     d_pairs, n_pairs, R, prof, d_qdesc, prof2);
   return hipGetLastError();
 }
 

@@ -67,11 +67,51 @@ constexpr int kIntraGridRescore = 512; // workgroups sweeping the rescoring list
 }  // namespace
 }  // namespace swdb
 
+// A prepared batch: device descriptors and profiles for one set of query
+// lengths, matrix, gaps and buffers, plus the captured launch graph.
+struct BatchPlan {
+  bool valid = false;
+  std::vector<int64_t> qoffs;
+  swdb::Matrix mat{};
+  int32_t go = 0, ge = 0, sat_limit = 0;
+  const uint8_t* d_queries = nullptr;
+  int32_t* d_out = nullptr;
+  int R = 0, W = 0, RR = 0, W2 = 0, W2r = 0;
+  int n_pairs = 0;
+  int64_t n_items = 0, n_long_items = 0, max_pair_work = 0, max_query_work = 0;
+  int64_t inter_cells = 0, intra_cells = 0;
+  int grid_b = 0, grid_long = 0;
+  std::vector<int32_t> zero_queries;
+  swdb::DevBuf<swdb::PairDesc> pairs;
+  swdb::DevBuf<swdb::QueryDesc> qdesc;
+  swdb::DevBuf<int2> items, long_items;
+  swdb::DevBuf<int64_t> qoffs_d;
+  swdb::DevBuf<uint32_t> prof;
+  swdb::DevBuf<int8_t> prof2;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  void release() {
+    drop_graph();
+    pairs.release(); qdesc.release(); items.release(); long_items.release();
+    qoffs_d.release(); prof.release(); prof2.release();
+    valid = false;
+  }
+};
+
 struct sw_db {
   int device = 0;
+  int n_cus = 256;
   int64_t n_seqs = 0, n_res = 0;
   swdb::Plan plan;
   std::vector<int32_t> long_ids;
+  std::vector<int32_t> long_len;    // by sequence id (only long ones set)
   int64_t long_residues = 0;
 
   // resident database
@@ -81,16 +121,22 @@ struct sw_db {
   swdb::DevBuf<uint4> rb;          // inter-task boundary rows, all bins
   swdb::DevBuf<uint8_t> res;       // contiguous residues (original order)
   swdb::DevBuf<int64_t> offs;
-  swdb::DevBuf<int32_t> d_long_ids;
+  swdb::DevBuf<int2> d_long_items;   // {sid, 0} for the long list
   swdb::DevBuf<int2> rb_long;      // intra-task boundary rows, per workgroup
   swdb::DevBuf<int2> rb_resc;
-  swdb::DevBuf<int32_t> flags;     // [0] count, [1..] rescoring list
+  swdb::DevBuf<int32_t> flags;     // [0] count, [2..] {sid, query} rescoring list
 
   // per-query buffers, grown on demand
   swdb::DevBuf<uint32_t> prof;
   swdb::DevBuf<int8_t> prof2;
   swdb::DevBuf<uint8_t> q_stage;
   swdb::DevBuf<int32_t> out_stage;
+
+  BatchPlan batch;
+  swdb::DevBuf<uint4> rb_batch;    // per-workgroup boundary rows of the batched kernel
+  swdb::DevBuf<int32_t> counter;   // work-queue head of the batched kernel
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool use_graphs = true;
 
   hipStream_t own_stream = nullptr;  // sync API
   hipStream_t aux_stream = nullptr;  // long-sequence kernel, overlapped
@@ -121,10 +167,11 @@ void destroy(sw_db* db) {
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
   if (db->aux_stream) (void)hipStreamSynchronize(db->aux_stream);
   db->packed.release(); db->bins.release(); db->slot_seq.release(); db->rb.release();
-  db->res.release(); db->offs.release(); db->d_long_ids.release(); db->rb_long.release();
+  db->res.release(); db->offs.release(); db->d_long_items.release(); db->rb_long.release();
   db->rb_resc.release(); db->flags.release(); db->prof.release(); db->prof2.release();
   db->q_stage.release(); db->out_stage.release();
-  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join})
+  db->batch.release(); db->rb_batch.release(); db->counter.release();
+  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out})
     if (*e) (void)hipEventDestroy(*e);
   for (auto& t : db->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
   for (hipEvent_t e : db->ev_pool) (void)hipEventDestroy(e);
@@ -212,6 +259,19 @@ void time_end(sw_db* db, int idx, hipStream_t s) {
   (void)hipEventRecord(db->timed[(size_t)idx].b, s);
 }
 
+// The rescoring list: flags[0] is the count, {sid, query} pairs start at
+// flags + 2 (8-byte aligned).
+int2* flag_list(sw_db* db) { return reinterpret_cast<int2*>(db->flags.p + 2); }
+
+hipError_t reserve_flags(sw_db* db, int64_t entries) {
+  return db->flags.reserve((size_t)(2 + 2 * std::max<int64_t>(entries, 1)));
+}
+
+hipError_t reserve_long_scratch(sw_db* db, int grid) {
+  return db->rb_long.reserve((size_t)std::max(grid, 1) *
+                             (size_t)std::max<int32_t>(db->plan.max_long_len, 1));
+}
+
 // Enqueues one query's search on stream s.  All arguments validated.
 int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
                    int32_t ge, int32_t* d_out, hipStream_t s) {
@@ -248,7 +308,10 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   ia.res = db->res.p;
   ia.offs = db->offs.p;
   ia.prof2 = db->prof2.p;
-  ia.m_pad2 = m_pad2;
+  ia.q0.prof2_off = 0;
+  ia.q0.out_off = 0;
+  ia.q0.m_pad2 = m_pad2;
+  ia.queries = nullptr;
   ia.go = go;
   ia.ge = ge;
   ia.out = d_out;
@@ -258,13 +321,15 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
     if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
       return hip_fail(e, "stream wait");
     IntraArgs la = ia;
-    la.items = db->d_long_ids.p;
+    la.items = db->d_long_items.p;
     la.count_ptr = nullptr;
     la.count = (int32_t)n_long;
+    const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
+    if ((e = reserve_long_scratch(db, grid)) != hipSuccess)
+      return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
     la.scratch = db->rb_long.p;
     la.scratch_stride = std::max<int64_t>(db->plan.max_long_len, 1);
-    la.n_pass = (m + 64 * RR - 1) / (64 * RR);
-    const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
+    la.q0.n_pass = (m + 64 * RR - 1) / (64 * RR);
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
     if ((e = launch_intra(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
@@ -288,7 +353,7 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   a.slot_seq = db->slot_seq.p;
   a.out = d_out;
   a.flag_count = db->flags.p;
-  a.flag_list = db->flags.p + 1;
+  a.flag_list = flag_list(db);
   a.sat_limit = db->sat_limit;
   const int n_bins = (int)db->plan.n_bins;
   if (n_bins > 0) {
@@ -298,12 +363,12 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
     ++db->stats.n_inter_launches;
     // exact rescoring of sequences whose 16-bit score saturated
     IntraArgs ra = ia;
-    ra.items = db->flags.p + 1;
+    ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;
     ra.count = 0;
     ra.scratch = db->rb_resc.p;
     ra.scratch_stride = std::max<int64_t>(db->plan.max_bin_len, 1);
-    ra.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
+    ra.q0.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
     const int tr = time_begin(db, kTimeRescore, s);
     if ((e = launch_intra(RRr, W2r, kIntraGridRescore, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
@@ -318,6 +383,263 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   const int64_t long_res = db->long_residues;
   db->stats.inter_cells += (int64_t)m * (db->n_res - long_res);
   db->stats.intra_cells += (int64_t)m * long_res;
+  return SW_OK;
+}
+
+// Builds (or keeps) the batch plan for these queries, matrix, gaps and
+// buffers: pairs of length-sorted queries, pair and per-query descriptors,
+// the (pair, half bin) work list costliest first, and the (sequence, query)
+// list of long-sequence items.
+int prepare_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
+                  const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out) {
+  BatchPlan& B = db->batch;
+  const int R = db->opt_rows ? db->opt_rows : 32;
+  const int W = (db->opt_waves == 4 || db->opt_waves == 8) ? db->opt_waves : 8;
+  std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
+  if (B.valid && B.qoffs == qv && memcmp(&B.mat, &mat, sizeof(mat)) == 0 && B.go == go &&
+      B.ge == ge && B.d_queries == d_queries && B.d_out == d_out && B.R == R && B.W == W &&
+      B.sat_limit == db->sat_limit)
+    return SW_OK;
+  B.release();
+  hipError_t e;
+  std::vector<int32_t> order;
+  std::vector<int64_t> ms(nq);
+  B.zero_queries.clear();
+  for (int32_t q = 0; q < nq; ++q) {
+    ms[q] = qoffs[q + 1] - qoffs[q];
+    if (ms[q] > 0) order.push_back(q);
+    else B.zero_queries.push_back(q);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return ms[a] > ms[b]; });
+  const int n_nz = (int)order.size();
+  // pairs of adjacent lengths
+  std::vector<PairDesc> pairs;
+  int64_t prof_dw = 0;
+  for (int i = 0; i < n_nz; i += 2) {
+    PairDesc pd{};
+    pd.qa = order[i];
+    pd.qb = i + 1 < n_nz ? order[i + 1] : -1;
+    pd.n_strips = (int32_t)((ms[pd.qa] + R - 1) / R);
+    pd.prof_off = prof_dw;
+    prof_dw += (int64_t)pd.n_strips * R * kBatchRowDwords;
+    B.max_pair_work = std::max<int64_t>(B.max_pair_work, (int64_t)pd.n_strips * R * kBatchRowDwords);
+    pairs.push_back(pd);
+  }
+  // intra-task parameters from the median query length
+  const int64_t m_med = n_nz ? ms[order[n_nz / 2]] : 1;
+  int RR = 8, W2 = 1, RRd = 8, W2r = 1;
+  pick_intra(db, (int)m_med, 8, &RR, &W2);
+  pick_intra(db, (int)m_med, 2, &RRd, &W2r);
+  (void)RRd;
+  std::vector<QueryDesc> qd((size_t)std::max(nq, 1));
+  int64_t prof2_bytes = 0;
+  for (int32_t q = 0; q < nq; ++q) {
+    const int64_t m = std::max<int64_t>(ms[q], 1);
+    qd[q].m_pad2 = (int32_t)((m + 511) / 512 * 512);
+    qd[q].n_pass = (int32_t)((m + 64 * RR - 1) / (64 * RR));
+    qd[q].prof2_off = prof2_bytes;
+    qd[q].out_off = (int64_t)q * db->n_seqs;
+    prof2_bytes += (int64_t)kIntraCodes * qd[q].m_pad2;
+    if (ms[q] > 0) B.max_query_work = std::max<int64_t>(B.max_query_work, (int64_t)kIntraCodes * qd[q].m_pad2);
+  }
+  // (pair, half bin) items, costliest first
+  const int64_t n_hb = 2 * db->plan.n_bins;
+  std::vector<int2> items;
+  items.reserve((size_t)(n_hb * (int64_t)pairs.size()));
+  for (int64_t hb = 0; hb < n_hb; ++hb)
+    for (int p = 0; p < (int)pairs.size(); ++p) items.push_back(make_int2(p, (int)hb));
+  const std::vector<int64_t>& bins = db->plan.bins;
+  auto cost = [&](const int2& it) {
+    return (int64_t)pairs[it.x].n_strips * (bins[(size_t)(it.y >> 1) * 4 + 2] / 4 + 2 * W);
+  };
+  std::stable_sort(items.begin(), items.end(),
+                   [&](const int2& a, const int2& b) { return cost(a) > cost(b); });
+  // (long sequence, query) items, costliest first
+  std::vector<int2> litems;
+  for (int64_t t = 0; t < db->plan.n_long; ++t)
+    for (int32_t q : order) litems.push_back(make_int2(db->long_ids[(size_t)t], q));
+  const int64_t* offs = nullptr;
+  (void)offs;
+  auto lcost = [&](const int2& it) {
+    return ms[it.y] * (int64_t)db->long_len[(size_t)it.x];
+  };
+  std::stable_sort(litems.begin(), litems.end(),
+                   [&](const int2& a, const int2& b) { return lcost(a) > lcost(b); });
+  B.inter_cells = B.intra_cells = 0;
+  for (int32_t q : order) {
+    B.inter_cells += ms[q] * (db->n_res - db->long_residues);
+    B.intra_cells += ms[q] * db->long_residues;
+  }
+
+  auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+    return bytes ? hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+  };
+  if ((e = B.pairs.reserve(std::max<size_t>(pairs.size(), 1))) != hipSuccess ||
+      (e = B.qdesc.reserve(qd.size())) != hipSuccess ||
+      (e = B.items.reserve(std::max<size_t>(items.size(), 1))) != hipSuccess ||
+      (e = B.long_items.reserve(std::max<size_t>(litems.size(), 1))) != hipSuccess ||
+      (e = B.qoffs_d.reserve(qv.size())) != hipSuccess ||
+      (e = B.prof.reserve((size_t)std::max<int64_t>(prof_dw, 1))) != hipSuccess ||
+      (e = B.prof2.reserve((size_t)std::max<int64_t>(prof2_bytes, 16))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("batch allocation: ") + hipGetErrorString(e));
+  if ((e = put(B.pairs.p, pairs.data(), pairs.size() * sizeof(PairDesc))) != hipSuccess ||
+      (e = put(B.qdesc.p, qd.data(), qd.size() * sizeof(QueryDesc))) != hipSuccess ||
+      (e = put(B.items.p, items.data(), items.size() * sizeof(int2))) != hipSuccess ||
+      (e = put(B.long_items.p, litems.data(), litems.size() * sizeof(int2))) != hipSuccess ||
+      (e = put(B.qoffs_d.p, qv.data(), qv.size() * sizeof(int64_t))) != hipSuccess)
+    return hip_fail(e, "batch descriptors");
+  B.n_pairs = (int)pairs.size();
+  B.n_items = (int64_t)items.size();
+  B.n_long_items = (int64_t)litems.size();
+  B.R = R;
+  B.W = W;
+  B.RR = RR;
+  B.W2 = W2;
+  B.W2r = W2r;
+  B.grid_b = db->n_cus * batch_workgroups_per_cu(R, W);
+  B.grid_long = (int)std::min<int64_t>(B.n_long_items, kIntraGridLong);
+  if ((e = db->rb_batch.reserve((size_t)B.grid_b * (size_t)(db->plan.max_bin_len / 4) * 128)) != hipSuccess ||
+      (e = db->counter.reserve(1)) != hipSuccess ||
+      (e = reserve_flags(db, (db->plan.n_bins * (int64_t)SW_BIN_SEQS) * std::max(n_nz, 1))) != hipSuccess ||
+      (e = reserve_long_scratch(db, std::max(B.grid_long, 1))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("batch scratch: ") + hipGetErrorString(e));
+  B.qoffs = qv;
+  B.mat = mat;
+  B.go = go;
+  B.ge = ge;
+  B.sat_limit = db->sat_limit;
+  B.d_queries = d_queries;
+  B.d_out = d_out;
+  B.valid = true;
+  return SW_OK;
+}
+
+// Enqueues the prepared batch on stream s (graph capture safe: kernels only).
+int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
+  BatchPlan& B = db->batch;
+  hipError_t e;
+  const int64_t n = db->n_seqs;
+  const int t_total = time_begin(db, kTimeTotal, s);
+  if ((e = launch_fill(db->counter.p, 1, 0, s)) != hipSuccess ||
+      (e = launch_fill(db->flags.p, 1, 0, s)) != hipSuccess)
+    return hip_fail(e, "reset");
+  for (int32_t q : B.zero_queries)
+    if ((e = launch_fill(B.d_out + (size_t)q * n, n, 0, s)) != hipSuccess) return hip_fail(e, "fill");
+  const int nq = (int)B.qoffs.size() - 1;
+  if (B.n_pairs == 0) {
+    time_end(db, t_total, s);
+    return SW_OK;
+  }
+  if ((e = launch_batch_profiles(B.d_queries, B.qoffs_d.p, nq, B.mat, B.pairs.p, B.n_pairs, B.R,
+                                 std::max(B.max_pair_work, B.max_query_work), B.prof.p, B.qdesc.p,
+                                 B.prof2.p, s)) != hipSuccess)
+    return hip_fail(e, "batch profiles");
+  IntraArgs ia{};
+  ia.res = db->res.p;
+  ia.offs = db->offs.p;
+  ia.prof2 = B.prof2.p;
+  ia.queries = B.qdesc.p;
+  ia.go = B.go;
+  ia.ge = B.ge;
+  ia.out = B.d_out;
+  if (B.n_long_items > 0) {
+    if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
+      return hip_fail(e, "stream wait");
+    IntraArgs la = ia;
+    la.items = B.long_items.p;
+    la.count = (int32_t)B.n_long_items;
+    la.scratch = db->rb_long.p;
+    la.scratch_stride = std::max<int64_t>(db->plan.max_long_len, 1);
+    const int tl = time_begin(db, kTimeIntra, db->aux_stream);
+    if ((e = launch_intra(B.RR, B.W2, B.grid_long, la, db->aux_stream)) != hipSuccess)
+      return hip_fail(e, "intra-task kernel");
+    time_end(db, tl, db->aux_stream);
+    if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess) return hip_fail(e, "event");
+  }
+  if (db->plan.n_bins > 0) {
+    BatchArgs ba{};
+    ba.res = db->packed.p;
+    ba.bins = db->bins.p;
+    ba.items = B.items.p;
+    ba.n_items = (int32_t)B.n_items;
+    ba.counter = db->counter.p;
+    ba.pairs = B.pairs.p;
+    ba.prof = B.prof.p;
+    const uint32_t go16 = (uint32_t)std::min<int32_t>(B.go, 65535);
+    const uint32_t ge16 = (uint32_t)std::min<int32_t>(B.ge, 65535);
+    ba.go2 = go16 | (go16 << 16);
+    ba.ge2 = ge16 | (ge16 << 16);
+    ba.rb = db->rb_batch.p;
+    ba.rb_stride = (int64_t)(db->plan.max_bin_len / 4) * 128;
+    ba.slot_seq = db->slot_seq.p;
+    ba.out = B.d_out;
+    ba.n_seqs = n;
+    ba.flag_count = db->flags.p;
+    ba.flag_list = flag_list(db);
+    ba.sat_limit = B.sat_limit;
+    const int ti = time_begin(db, kTimeInter, s);
+    if ((e = launch_batch(B.R, B.W, B.grid_b, ba, s)) != hipSuccess)
+      return hip_fail(e, "batched inter-task kernel");
+    time_end(db, ti, s);
+    IntraArgs ra = ia;
+    ra.items = flag_list(db);
+    ra.count_ptr = db->flags.p;
+    ra.scratch = db->rb_resc.p;
+    ra.scratch_stride = std::max<int64_t>(db->plan.max_bin_len, 1);
+    const int tr = time_begin(db, kTimeRescore, s);
+    if ((e = launch_intra(B.RR, B.W2r, kIntraGridRescore, ra, s)) != hipSuccess)
+      return hip_fail(e, "rescoring kernel");
+    time_end(db, tr, s);
+  }
+  if (B.n_long_items > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
+    return hip_fail(e, "stream wait");
+  time_end(db, t_total, s);
+  return SW_OK;
+}
+
+// Runs a batch: the kernels are captured once into a HIP graph on the
+// handle's own stream and replayed while the plan stays the same; the
+// caller's stream is ordered before and after with events.
+int run_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
+              const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out, hipStream_t s) {
+  hipError_t e;
+  if (db->n_seqs == 0 || nq == 0) return SW_OK;
+  int rc = prepare_batch(db, d_queries, qoffs, nq, mat, go, ge, d_out);
+  if (rc != SW_OK) return rc;
+  BatchPlan& B = db->batch;
+  hipStream_t os = db->own_stream;
+  if ((e = hipEventRecord(db->ev_in, s)) != hipSuccess ||
+      (e = hipStreamWaitEvent(os, db->ev_in, 0)) != hipSuccess)
+    return hip_fail(e, "stream order");
+  if (db->timing || !db->use_graphs) {
+    rc = enqueue_batch_kernels(db, os);
+    if (rc != SW_OK) return rc;
+  } else {
+    if (!B.exec) {
+      if ((e = hipStreamBeginCapture(os, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "graph capture");
+      rc = enqueue_batch_kernels(db, os);
+      hipGraph_t g = nullptr;
+      e = hipStreamEndCapture(os, &g);
+      if (rc != SW_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+      if (e != hipSuccess) return hip_fail(e, "graph capture");
+      B.graph = g;
+      if ((e = hipGraphInstantiate(&B.exec, g, nullptr, nullptr, 0)) != hipSuccess) {
+        B.drop_graph();
+        return hip_fail(e, "graph instantiation");
+      }
+    }
+    if ((e = hipGraphLaunch(B.exec, os)) != hipSuccess) return hip_fail(e, "graph launch");
+  }
+  if ((e = hipEventRecord(db->ev_out, os)) != hipSuccess ||
+      (e = hipStreamWaitEvent(s, db->ev_out, 0)) != hipSuccess)
+    return hip_fail(e, "stream order");
+  db->stats.rows = B.R;
+  db->stats.waves = B.W;
+  db->stats.n_inter_launches += db->plan.n_bins > 0 ? 1 : 0;
+  db->stats.inter_cells += B.inter_cells;
+  db->stats.intra_cells += B.intra_cells;
   return SW_OK;
 }
 
@@ -343,7 +665,10 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   db->n_res = offsets[n_seqs];
   const Plan& P = db->plan;
   db->long_ids.resize((size_t)P.n_long);
+  db->long_len.assign((size_t)std::max<int64_t>(n_seqs, 1), 0);
   for (int64_t t = 0; t < P.n_long; ++t) {
+    db->long_len[(size_t)P.order[(size_t)t]] =
+        (int32_t)(offsets[P.order[(size_t)t] + 1] - offsets[P.order[(size_t)t]]);
     db->long_ids[(size_t)t] = P.order[(size_t)t];
     db->long_residues += offsets[P.order[(size_t)t] + 1] - offsets[P.order[(size_t)t]];
   }
@@ -361,6 +686,8 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
     return fail(SW_ENOMEM, "host staging allocation failed");
   }
   fill_layout(residues, offsets, P, h_packed.data(), h_bins.data(), h_slots.data(), h_long.data());
+  std::vector<int2> h_long_items(h_long.size());
+  for (size_t t = 0; t < h_long.size(); ++t) h_long_items[t] = make_int2(h_long[t], 0);
 
   auto alloc_fail = [&](hipError_t err, const char* what) {
     destroy(db);
@@ -372,15 +699,11 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   if ((e = db->rb.reserve((size_t)P.boundary_uint4)) != hipSuccess) return alloc_fail(e, "boundary");
   if ((e = db->res.reserve((size_t)db->n_res)) != hipSuccess) return alloc_fail(e, "residues");
   if ((e = db->offs.reserve((size_t)n_seqs + 1)) != hipSuccess) return alloc_fail(e, "offsets");
-  if ((e = db->d_long_ids.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
-  const int64_t long_grid = std::min<int64_t>(P.n_long, kIntraGridLong);
-  if ((e = db->rb_long.reserve((size_t)std::max<int64_t>(long_grid, 1) *
-                               std::max<int32_t>(P.max_long_len, 1))) != hipSuccess)
-    return alloc_fail(e, "long scratch");
+  if ((e = db->d_long_items.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
   if ((e = db->rb_resc.reserve((size_t)kIntraGridRescore * std::max<int32_t>(P.max_bin_len, 1))) !=
       hipSuccess)
     return alloc_fail(e, "rescore scratch");
-  if ((e = db->flags.reserve((size_t)P.n_bins * SW_BIN_SEQS + 1)) != hipSuccess)
+  if ((e = reserve_flags(db, (int64_t)P.n_bins * SW_BIN_SEQS)) != hipSuccess)
     return alloc_fail(e, "flags");
 
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -392,7 +715,7 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
       (e = up(db->slot_seq.p, h_slots.data(), h_slots.size() * 4)) != hipSuccess ||
       (e = up(db->res.p, residues, (size_t)db->n_res)) != hipSuccess ||
       (e = up(db->offs.p, offsets, ((size_t)n_seqs + 1) * 8)) != hipSuccess ||
-      (e = up(db->d_long_ids.p, h_long.data(), h_long.size() * 4)) != hipSuccess) {
+      (e = up(db->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess) {
     destroy(db);
     return hip_fail(e, "database upload");
   }
@@ -401,7 +724,13 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
     destroy(db);
     return hip_fail(e, "stream creation");
   }
-  for (hipEvent_t* ev : {&db->ev_fork, &db->ev_join})
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, db->device) == hipSuccess &&
+        ncu > 0)
+      db->n_cus = ncu;
+  }
+  for (hipEvent_t* ev : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out})
     if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) {
       destroy(db);
       return hip_fail(e, "event creation");
@@ -511,15 +840,10 @@ int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* qu
   DeviceGuard g(db->device);
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
-  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  for (int32_t q = 0; q < n_queries; ++q) {
-    const int32_t m = (int32_t)(query_offsets[q + 1] - query_offsets[q]);
-    rc = enqueue_search(db, d_queries + query_offsets[q], m, mat, gap_open, gap_extend,
-                        d_out_scores + (size_t)q * db->n_seqs, s);
-    if (rc != SW_OK) return rc;
-  }
-  set_error("");
-  return SW_OK;
+  rc = run_batch(db, d_queries, query_offsets, n_queries, mat, gap_open, gap_extend, d_out_scores,
+                 reinterpret_cast<hipStream_t>(hip_stream));
+  if (rc == SW_OK) set_error("");
+  return rc;
 }
 
 int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offsets,
@@ -537,8 +861,9 @@ int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offs
   DeviceGuard g(db->device);
   hipError_t e;
   hipStream_t s = db->own_stream;
+  const size_t out_n = (size_t)n_queries * (size_t)db->n_seqs;
   if ((e = db->q_stage.reserve((size_t)std::max<int64_t>(total, 1))) != hipSuccess ||
-      (e = db->out_stage.reserve((size_t)std::max<int64_t>(db->n_seqs, 1))) != hipSuccess)
+      (e = db->out_stage.reserve(std::max<size_t>(out_n, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
   if (total > 0 &&
       (e = hipMemcpyAsync(db->q_stage.p, queries, (size_t)total, hipMemcpyHostToDevice, s)) !=
@@ -546,16 +871,12 @@ int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offs
     return hip_fail(e, "query upload");
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
-  for (int32_t q = 0; q < n_queries; ++q) {
-    const int32_t m = (int32_t)(query_offsets[q + 1] - query_offsets[q]);
-    rc = enqueue_search(db, db->q_stage.p + query_offsets[q], m, mat, gap_open, gap_extend,
-                        db->out_stage.p, s);
-    if (rc != SW_OK) { (void)hipStreamSynchronize(s); return rc; }
-    if (db->n_seqs > 0 &&
-        (e = hipMemcpyAsync(out_scores + (size_t)q * db->n_seqs, db->out_stage.p,
-                            (size_t)db->n_seqs * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return hip_fail(e, "score download");
-  }
+  rc = run_batch(db, db->q_stage.p, query_offsets, n_queries, mat, gap_open, gap_extend,
+                 db->out_stage.p, s);
+  if (rc != SW_OK) { (void)hipStreamSynchronize(s); return rc; }
+  if (out_n > 0 && (e = hipMemcpyAsync(out_scores, db->out_stage.p, out_n * 4, hipMemcpyDeviceToHost,
+                                       s)) != hipSuccess)
+    return hip_fail(e, "score download");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
   set_error("");
   return SW_OK;
@@ -588,6 +909,11 @@ int sw_set_option(sw_db* db, int32_t key, int64_t value) {
       if (value != 0 && value != 2 && value != 4 && value != 8)
         return fail(SW_EINVAL, "intra rows must be 0, 2, 4 or 8");
       db->opt_intra_rows = (int32_t)value;
+      return SW_OK;
+    case SW_OPT_GRAPHS:
+      if (value != 0 && value != 1) return fail(SW_EINVAL, "graphs must be 0 or 1");
+      db->use_graphs = value != 0;
+      db->batch.drop_graph();
       return SW_OK;
     case SW_OPT_INTRA_WAVES:
       if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)

@@ -259,3 +259,89 @@ def test_full_size_plain_workload_sampled(sw):
         assert (got[qi] >= 0).all()
         assert (got[qi] <= np.minimum(len(q), lens) * 11).all()
     say("sampled %d x %d scores ok" % (len(w.queries), len(ids)))
+
+
+# --------------------------------------------------------------- batched form
+def _queries(seed, lengths):
+    rng = np.random.default_rng(seed)
+    return [swinputs.random_residues(int(m), rng) for m in lengths]
+
+
+@pytest.mark.parametrize("graphs", [0, 1])
+def test_batch_matches_oracle(sw, graphs):
+    res, offs = _ragged_db(20)
+    qs = _queries(21, [0, 1, 17, 144, 145, 600, 33, 1500, 64, 200, 0, 999])   # odd count, empties
+    say("batch, graphs=%d" % graphs)
+    with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_GRAPHS, graphs)
+        got = db.search_batch(qs, B62, 10, 2)
+    for q, row in zip(qs, got):
+        assert (row == _oracle(q, res, offs)).all()
+
+
+@pytest.mark.parametrize("rows,waves", [(16, 4), (16, 8), (32, 4), (32, 8)])
+def test_batch_strip_options(sw, rows, waves):
+    res, offs = _ragged_db(22)
+    qs = _queries(23, [300, 280, 90, 31])
+    say("batch rows=%d waves=%d" % (rows, waves))
+    with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_ROWS, rows)
+        db.set_option(sw.SW_OPT_WAVES, waves)
+        got = db.search_batch(qs, B62, 11, 1)
+    for q, row in zip(qs, got):
+        assert (row == _oracle(q, res, offs, B62, 11, 1)).all()
+
+
+def test_batch_long_and_rescoring_items(sw):
+    """Long list x all queries and the (sequence, query) rescoring list."""
+    res, offs = _ragged_db(24)
+    qs = _queries(25, [700, 120, 333])
+    say("batch long + rescoring")
+    for t_long, limit in ((100, 32767), (10**6, 35), (300, 0)):
+        with sw.Database(res, offs, long_threshold=t_long) as db:
+            db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
+            got = db.search_batch(qs, B62, 10, 2)
+        for q, row in zip(qs, got):
+            assert (row == _oracle(q, res, offs)).all(), (t_long, limit)
+
+
+def test_batch_graph_replays_with_eager_work_between(sw):
+    """Replays of the captured batch graph, with single searches and host
+    synchronisation between them, each equal the eager result."""
+    import torch
+    res, offs = _ragged_db(26)
+    qs = _queries(27, [150, 400, 90, 260, 51])
+    cat = torch.from_numpy(np.concatenate(qs)).cuda()
+    qoffs = np.zeros(len(qs) + 1, np.int64)
+    np.cumsum([len(q) for q in qs], out=qoffs[1:])
+    say("graph replays")
+    with sw.Database(res, offs, long_threshold=500) as db:
+        db.set_option(sw.SW_OPT_GRAPHS, 0)
+        d_eager = torch.full((len(qs), db.n_seqs), -1, dtype=torch.int32, device="cuda")
+        db.search_batch_async(cat, qoffs, B62, 10, 2, d_eager)
+        torch.cuda.synchronize()
+        eager = d_eager.cpu().numpy()
+        db.set_option(sw.SW_OPT_GRAPHS, 1)
+        d_out = torch.full((len(qs), db.n_seqs), -1, dtype=torch.int32, device="cuda")
+        for rep in range(4):
+            d_out.fill_(-1)
+            db.search_batch_async(cat, qoffs, B62, 10, 2, d_out)
+            torch.cuda.synchronize()
+            assert (d_out.cpu().numpy() == eager).all(), rep
+            single = db.search(qs[rep], B62, 10, 2)        # eager work between replays
+            assert (single == eager[rep]).all()
+    for q, row in zip(qs, eager):
+        assert (row == _oracle(q, res, offs)).all()
+
+
+def test_batch_workload_scaled(sw):
+    """The batched workload's recipe on a 2% database: 20 + 200 queries."""
+    w = swinputs.config("batched", scale=0.02)
+    rng = np.random.default_rng(28)
+    ids = rng.choice(w.n_seqs, 40, replace=False)
+    say("batched 2%%: %d seqs, %d queries" % (w.n_seqs, len(w.queries)))
+    with sw.Database(w.residues, w.offsets) as db:
+        got = db.search_batch(w.queries, w.matrix, 10, 2)
+    for qi in range(0, len(w.queries), 7):
+        want = ocpu.search(w.queries[qi], w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
+        assert (got[qi][ids] == want).all(), qi
