@@ -181,15 +181,43 @@ typedef struct sw_stats {
 /* Waits for the recorded work, fills *out and resets the counters. */
 int sw_get_stats(sw_db* db, sw_stats* out);
 
+/* ----------------------------------------------------------- search contexts
+ * A database handle carries one search context; sw_ctx_create adds more, each
+ * with private scratch (boundary rows, profiles, rescoring list, batch plan),
+ * streams and options, so that several searches of one resident database can
+ * be in flight at once - one call at a time per context, any number of
+ * contexts concurrently (the serving loop keeps one per in-flight request).
+ * A context must be freed before its database.  Options start as the
+ * database handle's at creation.
+ *   sw_ctx_bytes : device bytes of fixed scratch one context allocates (per-
+ *                  query buffers grow on top of it), or -1 for a NULL db. */
+typedef struct sw_ctx sw_ctx;
+int sw_ctx_create(sw_db* db, sw_ctx** out_ctx);
+void sw_ctx_free(sw_ctx* ctx);
+int64_t sw_ctx_bytes(const sw_db* db);
+int sw_ctx_search_async(sw_ctx* ctx, const uint8_t* d_query, int32_t query_len,
+                        const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                        int32_t* d_out_scores, void* hip_stream);
+int sw_ctx_search_batch_async(sw_ctx* ctx, const uint8_t* d_queries,
+                              const int64_t* query_offsets, int32_t n_queries,
+                              const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                              int32_t* d_out_scores, void* hip_stream);
+int sw_ctx_set_option(sw_ctx* ctx, int32_t key, int64_t value);
+int sw_ctx_get_stats(sw_ctx* ctx, sw_stats* out);
+
+
 /* ------------------------------------------------------- host-only layout
  * The database layout, computed without touching any device (the same code
  * sw_db_load uses).  Sequences are stable-sorted by decreasing length; those
- * with length >= long_threshold form the long list; the rest fill bins of
- * SW_BIN_SEQS = 128 consecutive sorted sequences, slot k of a bin being lane
- * k/2, half k%2.  A bin stores its residues position-major: dword
- * res_off + (p/4)*128 + k holds positions p..p+3 of slot k (byte p%4 = position
- * p), padded with code SW_PAD_CODE up to the bin length, a multiple of 4 and
- * at least SW_MIN_BIN_LEN.
+ * with length >= long_threshold form the long list (scored by the intra-task
+ * kernel in single searches); the rest fill the short bins of SW_BIN_SEQS =
+ * 128 consecutive sorted sequences, slot k of a bin being lane k/2, half k%2.
+ * The long sequences shorter than the very-long threshold (4 x long_threshold)
+ * also fill "long bins", stored after the short bins, which batched searches
+ * score with the inter-task kernel.  A bin stores its residues
+ * position-major: dword res_off + (p/4)*128 + k holds positions p..p+3 of slot
+ * k (byte p%4 = position p), padded with code SW_PAD_CODE up to the bin
+ * length, a multiple of 4 and at least SW_MIN_BIN_LEN.
  */
 #define SW_BIN_SEQS 128
 #define SW_PAD_CODE 24
@@ -197,13 +225,16 @@ int sw_get_stats(sw_db* db, sw_stats* out);
 
 typedef struct sw_plan_info {
   int64_t n_bins;          /* bins of short sequences */
+  int64_t n_long_bins;     /* bins of long sequences below the very-long threshold */
   int64_t n_long;          /* sequences in the long list */
+  int64_t n_very_long;     /* long sequences at or above the very-long threshold */
   int64_t packed_dwords;   /* size of the interleaved residue store */
   int64_t boundary_bytes;  /* inter-task boundary-row scratch for all bins */
   int32_t max_len;         /* longest sequence */
   int32_t max_bin_len;     /* longest bin (padded) */
   int32_t max_long_len;    /* longest sequence in the long list (0 if none) */
   int32_t long_threshold;  /* the threshold actually used */
+  int32_t very_long_threshold;
 } sw_plan_info;
 
 /* Validates offsets and fills *info.  residues may be NULL (codes are then
@@ -211,11 +242,11 @@ typedef struct sw_plan_info {
 int sw_plan(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
             int32_t long_threshold, sw_plan_info* info);
 
-/* Fills the host layout arrays sized from sw_plan:
+/* Fills the host layout arrays sized from sw_plan (nb = n_bins + n_long_bins):
  *   packed   : uint32_t[packed_dwords]
- *   bin_desc : int64_t[n_bins * 4] = {res_off (dwords), boundary offset
+ *   bin_desc : int64_t[nb * 4] = {res_off (dwords), boundary offset
  *              (16-byte units), length, first slot} per bin
- *   slot_seq : int32_t[n_bins * 128], original sequence index or -1
+ *   slot_seq : int32_t[nb * 128], original sequence index or -1
  *   long_ids : int32_t[n_long], original indices, longest first */
 int sw_pack(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
             int32_t long_threshold, uint32_t* packed, int64_t* bin_desc,

@@ -17,7 +17,7 @@ from ._native import (SwError, SW_ALPHA, SW_BIN_SEQS, SW_PAD_CODE, SW_MIN_BIN_LE
                       SW_DEFAULT_LONG_THRESHOLD, SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS,
                       SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES, SW_OPT_GRAPHS)
 
-__all__ = ["Database", "SwError", "plan", "pack", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
+__all__ = ["Database", "Context", "SwError", "plan", "pack", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
            "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
            "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS"]
 
@@ -67,13 +67,14 @@ def pack(residues, offsets, long_threshold: int = 0) -> dict:
     res, offs = _u8(residues), _i64(offsets)
     info = plan(offs, long_threshold, res)
     packed = np.zeros(max(info["packed_dwords"], 1), dtype=np.uint32)
-    bins = np.zeros((max(info["n_bins"], 1), 4), dtype=np.int64)
-    slots = np.zeros(max(info["n_bins"] * SW_BIN_SEQS, 1), dtype=np.int32)
+    nb = info["n_bins"] + info["n_long_bins"]
+    bins = np.zeros((max(nb, 1), 4), dtype=np.int64)
+    slots = np.zeros(max(nb * SW_BIN_SEQS, 1), dtype=np.int32)
     long_ids = np.zeros(max(info["n_long"], 1), dtype=np.int32)
     _native.check(_native.lib().sw_pack(_ptr(res), _ptr(offs), len(offs) - 1, long_threshold,
                                         _ptr(packed), _ptr(bins), _ptr(slots), _ptr(long_ids)))
     return {"info": info, "packed": packed[:info["packed_dwords"]],
-            "bins": bins[:info["n_bins"]], "slot_seq": slots[:info["n_bins"] * SW_BIN_SEQS],
+            "bins": bins[:nb], "slot_seq": slots[:nb * SW_BIN_SEQS],
             "long_ids": long_ids[:info["n_long"]]}
 
 
@@ -158,5 +159,60 @@ class Database:
         qoffs = _i64(query_offsets)
         m = _matrix(matrix)
         _native.check(_native.lib().sw_search_batch_async(
+            self._h, _ptr(d_queries), _ptr(qoffs), len(qoffs) - 1, _ptr(m), gap_open,
+            gap_extend, _ptr(d_out), _stream_handle(stream)))
+
+    def context(self) -> "Context":
+        """A new search context: private scratch, so searches on different
+        contexts can be in flight at once."""
+        return Context(self)
+
+    def context_bytes(self) -> int:
+        """Device bytes of fixed scratch one extra context allocates."""
+        return int(_native.lib().sw_ctx_bytes(self._h))
+
+
+class Context:
+    """A search context of a Database (sw_ctx_*): device-buffer searches that
+    may run concurrently with searches on other contexts."""
+
+    def __init__(self, db: Database):
+        h = ctypes.c_void_p()
+        _native.check(_native.lib().sw_ctx_create(db._h, ctypes.byref(h)))
+        self._h = h
+        self.db = db
+        self.n_seqs = db.n_seqs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _native.lib().sw_ctx_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_option(self, key: int, value: int):
+        _native.check(_native.lib().sw_ctx_set_option(self._h, key, int(value)))
+
+    def stats(self) -> dict:
+        st = _native.Stats()
+        _native.check(_native.lib().sw_ctx_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _native.Stats._fields_}
+
+    def search_async(self, d_query, matrix, gap_open: int, gap_extend: int, d_out,
+                     stream=None):
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_ctx_search_async(
+            self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
+            _ptr(d_out), _stream_handle(stream)))
+
+    def search_batch_async(self, d_queries, query_offsets, matrix, gap_open: int,
+                           gap_extend: int, d_out, stream=None):
+        qoffs = _i64(query_offsets)
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_ctx_search_batch_async(
             self._h, _ptr(d_queries), _ptr(qoffs), len(qoffs) - 1, _ptr(m), gap_open,
             gap_extend, _ptr(d_out), _stream_handle(stream)))

@@ -33,10 +33,12 @@ class SwError(RuntimeError):
 
 
 class PlanInfo(ctypes.Structure):
-    _fields_ = [("n_bins", ctypes.c_int64), ("n_long", ctypes.c_int64),
+    _fields_ = [("n_bins", ctypes.c_int64), ("n_long_bins", ctypes.c_int64),
+                ("n_long", ctypes.c_int64), ("n_very_long", ctypes.c_int64),
                 ("packed_dwords", ctypes.c_int64), ("boundary_bytes", ctypes.c_int64),
                 ("max_len", ctypes.c_int32), ("max_bin_len", ctypes.c_int32),
-                ("max_long_len", ctypes.c_int32), ("long_threshold", ctypes.c_int32)]
+                ("max_long_len", ctypes.c_int32), ("long_threshold", ctypes.c_int32),
+                ("very_long_threshold", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -62,6 +64,13 @@ SIGNATURES = {
     "sw_set_option": (ctypes.c_int, [P, I32, I64]),
     "sw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
     "sw_plan": (ctypes.c_int, [P, P, I64, I32, ctypes.POINTER(PlanInfo)]),
+    "sw_ctx_create": (ctypes.c_int, [P, ctypes.POINTER(P)]),
+    "sw_ctx_free": (None, [P]),
+    "sw_ctx_bytes": (I64, [P]),
+    "sw_ctx_search_async": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
+    "sw_ctx_search_batch_async": (ctypes.c_int, [P, P, P, I32, P, I32, I32, P, P]),
+    "sw_ctx_set_option": (ctypes.c_int, [P, I32, I64]),
+    "sw_ctx_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
     "sw_pack": (ctypes.c_int, [P, P, I64, I32, P, P, P, P]),
 }
 

@@ -58,20 +58,41 @@ int plan_layout(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
   while (n_long < n_seqs &&
          offsets[plan->order[n_long] + 1] - offsets[plan->order[n_long]] >= t_long)
     ++n_long;
+  // the very long sequences (a prefix of the long list) stay out of the long
+  // bins; with the 32-bit threshold t_vlong = 4 * t_long
+  const int64_t t_vlong = 4 * (int64_t)t_long;
+  int64_t n_vlong = 0;
+  while (n_vlong < n_long &&
+         offsets[plan->order[n_vlong] + 1] - offsets[plan->order[n_vlong]] >= t_vlong)
+    ++n_vlong;
   plan->n_long = n_long;
+  plan->n_vlong = n_vlong;
+  plan->very_long_threshold = (int32_t)std::min<int64_t>(t_vlong, INT32_MAX);
   plan->max_long_len = n_long ? (int32_t)(offsets[plan->order[0] + 1] - offsets[plan->order[0]]) : 0;
   const int64_t n_short = n_seqs - n_long;
   plan->n_bins = (n_short + SW_BIN_SEQS - 1) / SW_BIN_SEQS;
-  plan->bins.resize((size_t)plan->n_bins * 4);
+  plan->n_long_bins = (n_long - n_vlong + SW_BIN_SEQS - 1) / SW_BIN_SEQS;
+  const int64_t n_all = plan->n_bins + plan->n_long_bins;
+  plan->bins.resize((size_t)n_all * 4);
+  plan->bin_first.resize((size_t)n_all);
+  plan->bin_count.resize((size_t)n_all);
   int64_t res_off = 0, rb_off = 0;
   plan->max_bin_len = 0;
   plan->max_short_len = 0;
-  for (int64_t b = 0; b < plan->n_bins; ++b) {
+  plan->max_all_bin_len = 0;
+  for (int64_t b = 0; b < n_all; ++b) {
+    // short bins cover order[n_long ..), long bins order[n_vlong .. n_long)
+    const bool is_long = b >= plan->n_bins;
+    const int64_t lb = is_long ? b - plan->n_bins : b;
+    const int64_t first = (is_long ? n_vlong : n_long) + lb * SW_BIN_SEQS;
+    const int64_t end_ = is_long ? n_long : n_seqs;
+    plan->bin_first[(size_t)b] = first;
+    plan->bin_count[(size_t)b] = (int32_t)std::min<int64_t>(SW_BIN_SEQS, end_ - first);
     // the first sequence of a bin is its longest
-    int32_t first = plan->order[n_long + b * SW_BIN_SEQS];
-    int64_t l = offsets[first + 1] - offsets[first];
-    if (l > plan->max_short_len) plan->max_short_len = (int32_t)l;
-    int64_t len = std::max<int64_t>((l + 3) & ~int64_t(3), SW_MIN_BIN_LEN);
+    const int32_t sid0 = plan->order[(size_t)first];
+    const int64_t l = offsets[sid0 + 1] - offsets[sid0];
+    if (!is_long && l > plan->max_short_len) plan->max_short_len = (int32_t)l;
+    const int64_t len = std::max<int64_t>((l + 3) & ~int64_t(3), SW_MIN_BIN_LEN);
     int64_t* d = &plan->bins[(size_t)b * 4];
     d[0] = res_off;
     d[1] = rb_off;
@@ -79,7 +100,8 @@ int plan_layout(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
     d[3] = b * SW_BIN_SEQS;
     res_off += (len / 4) * SW_BIN_SEQS;
     rb_off += (len / 4) * 64 * 2;  // per 4 columns and lane: 2 x uint4 (H, F of 2 halves)
-    if (len > plan->max_bin_len) plan->max_bin_len = (int32_t)len;
+    if (!is_long && len > plan->max_bin_len) plan->max_bin_len = (int32_t)len;
+    if (len > plan->max_all_bin_len) plan->max_all_bin_len = (int32_t)len;
   }
   plan->packed_dwords = res_off;
   plan->boundary_uint4 = rb_off;
@@ -88,23 +110,22 @@ int plan_layout(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
 
 void fill_layout(const uint8_t* residues, const int64_t* offsets, const Plan& plan,
                  uint32_t* packed, int64_t* bin_desc, int32_t* slot_seq, int32_t* long_ids) {
-  const int64_t n_long = plan.n_long;
-  for (int64_t t = 0; t < n_long; ++t) long_ids[t] = plan.order[t];
-  const int64_t n_short = (int64_t)plan.order.size() - n_long;
+  for (int64_t t = 0; t < plan.n_long; ++t) long_ids[t] = plan.order[(size_t)t];
   if (bin_desc) memcpy(bin_desc, plan.bins.data(), plan.bins.size() * sizeof(int64_t));
-  for (int64_t b = 0; b < plan.n_bins; ++b) {
+  const int64_t n_all = plan.n_bins + plan.n_long_bins;
+  for (int64_t b = 0; b < n_all; ++b) {
     const int64_t* d = &plan.bins[(size_t)b * 4];
     const int64_t res_off = d[0], len = d[2];
     for (int k = 0; k < SW_BIN_SEQS; ++k) {
-      int64_t t = b * SW_BIN_SEQS + k;
-      int32_t sid = t < n_short ? plan.order[n_long + t] : -1;
+      const int64_t t = b * SW_BIN_SEQS + k;
+      const int32_t sid = k < plan.bin_count[(size_t)b] ? plan.order[(size_t)(plan.bin_first[(size_t)b] + k)] : -1;
       slot_seq[t] = sid;
       const uint8_t* s = sid >= 0 ? residues + offsets[sid] : nullptr;
-      int64_t sl = sid >= 0 ? offsets[sid + 1] - offsets[sid] : 0;
+      const int64_t sl = sid >= 0 ? offsets[sid + 1] - offsets[sid] : 0;
       for (int64_t p = 0; p < len; p += 4) {
         uint32_t w = 0;
         for (int x = 0; x < 4; ++x) {
-          uint32_t c = (p + x < sl) ? s[p + x] : (uint32_t)SW_PAD_CODE;
+          const uint32_t c = (p + x < sl) ? s[p + x] : (uint32_t)SW_PAD_CODE;
           w |= c << (8 * x);
         }
         packed[res_off + (p / 4) * SW_BIN_SEQS + k] = w;
@@ -125,7 +146,10 @@ int sw_plan(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
   int rc = swdb::plan_layout(residues, offsets, n_seqs, long_threshold, &plan);
   if (rc != SW_OK) return rc;
   info->n_bins = plan.n_bins;
+  info->n_long_bins = plan.n_long_bins;
   info->n_long = plan.n_long;
+  info->n_very_long = plan.n_vlong;
+  info->very_long_threshold = plan.very_long_threshold;
   info->packed_dwords = plan.packed_dwords;
   info->boundary_bytes = plan.boundary_uint4 * 16;
   info->max_len = plan.max_len;
@@ -143,7 +167,8 @@ int sw_pack(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
   plan.check_codes = true;
   int rc = swdb::plan_layout(residues, offsets, n_seqs, long_threshold, &plan);
   if (rc != SW_OK) return rc;
-  if ((plan.packed_dwords && !packed) || (plan.n_bins && (!bin_desc || !slot_seq)) ||
+  if ((plan.packed_dwords && !packed) ||
+      (plan.n_bins + plan.n_long_bins && (!bin_desc || !slot_seq)) ||
       (plan.n_long && !long_ids)) {
     swdb::set_error("an output array is NULL");
     return SW_EINVAL;

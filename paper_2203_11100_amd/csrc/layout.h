@@ -11,10 +11,17 @@ namespace swdb {
 struct Plan {
   bool check_codes = true;
   int32_t long_threshold = 0;
+  int32_t very_long_threshold = 0;
   int32_t max_len = 0, max_bin_len = 0, max_long_len = 0, max_short_len = 0;
-  int64_t n_long = 0, n_bins = 0, packed_dwords = 0, boundary_uint4 = 0;
+  int32_t max_all_bin_len = 0;  // including the long bins
+  int64_t n_long = 0, n_vlong = 0, n_bins = 0, n_long_bins = 0;
+  int64_t packed_dwords = 0, boundary_uint4 = 0;
   std::vector<int32_t> order;   // sorted original indices, longest first
-  std::vector<int64_t> bins;    // n_bins x {res_off, rb_off, len, slot0}
+  // bins: n_bins short bins, then n_long_bins bins of the long sequences
+  // below the very-long threshold; {res_off, rb_off, len, slot0} each
+  std::vector<int64_t> bins;
+  std::vector<int64_t> bin_first;   // index into `order` of each bin's first slot
+  std::vector<int32_t> bin_count;   // sequences in each bin
 };
 
 int plan_layout(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,

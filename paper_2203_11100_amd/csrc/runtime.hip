@@ -36,15 +36,37 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(SW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Streams whose pending work may still use a searcher's buffers; a buffer
+// is only replaced after they drain (set by the owning searcher).
+struct StreamSet {
+  hipStream_t s[3] = {nullptr, nullptr, nullptr};
+  bool used[3] = {false, false, false};   // the null stream is a valid entry
+  bool any = false;
+  void set(int i, hipStream_t x) {
+    s[i] = x;
+    used[i] = true;
+  }
+  void sync() const {
+    if (!any) {
+      (void)hipDeviceSynchronize();
+      return;
+    }
+    for (int i = 0; i < 3; ++i)
+      if (used[i]) (void)hipStreamSynchronize(s[i]);
+  }
+};
+
 template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t cap = 0;   // elements
+  const StreamSet* users = nullptr;
   hipError_t reserve(size_t n) {
     if (n <= cap && p) return hipSuccess;
     if (p) {
       // earlier kernels may still read the old buffer
-      (void)hipDeviceSynchronize();
+      if (users) users->sync();
+      else (void)hipDeviceSynchronize();
       (void)hipFree(p);
       p = nullptr;
       cap = 0;
@@ -55,7 +77,10 @@ struct DevBuf {
     return e;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (users) users->sync();
+      (void)hipFree(p);
+    }
     p = nullptr;
     cap = 0;
   }
@@ -105,101 +130,159 @@ struct BatchPlan {
   }
 };
 
-struct sw_db {
+namespace swdb {
+
+// The resident database, shared by every search context of a handle.
+struct DbData {
   int device = 0;
   int n_cus = 256;
   int64_t n_seqs = 0, n_res = 0;
-  swdb::Plan plan;
+  Plan plan;
   std::vector<int32_t> long_ids;
   std::vector<int32_t> long_len;    // by sequence id (only long ones set)
-  int64_t long_residues = 0;
+  int64_t long_residues = 0;        // all of the long list
+  int64_t vlong_residues = 0;       // its very long prefix
+  DevBuf<uint32_t> packed;          // interleaved bins
+  DevBuf<BinDesc> bins;
+  DevBuf<int32_t> slot_seq;
+  DevBuf<uint8_t> res;              // contiguous residues (original order)
+  DevBuf<int64_t> offs;
+  DevBuf<int2> d_long_items;        // {sid, 0} for the long list
+};
 
-  // resident database
-  swdb::DevBuf<uint32_t> packed;
-  swdb::DevBuf<swdb::BinDesc> bins;
-  swdb::DevBuf<int32_t> slot_seq;
-  swdb::DevBuf<uint4> rb;          // inter-task boundary rows, all bins
-  swdb::DevBuf<uint8_t> res;       // contiguous residues (original order)
-  swdb::DevBuf<int64_t> offs;
-  swdb::DevBuf<int2> d_long_items;   // {sid, 0} for the long list
-  swdb::DevBuf<int2> rb_long;      // intra-task boundary rows, per workgroup
-  swdb::DevBuf<int2> rb_resc;
-  swdb::DevBuf<int32_t> flags;     // [0] count, [2..] {sid, query} rescoring list
-
-  // per-query buffers, grown on demand
-  swdb::DevBuf<uint32_t> prof;
-  swdb::DevBuf<int8_t> prof2;
-  swdb::DevBuf<uint8_t> q_stage;
-  swdb::DevBuf<int32_t> out_stage;
-
+// Everything one search mutates: scratch buffers, streams, events, the
+// batch plan, options and counters.  One call at a time per searcher.
+struct Searcher {
+  DbData* d = nullptr;
+  StreamSet users;                  // streams this searcher's work runs on
+  DevBuf<uint4> rb;                 // inter-task boundary rows, all short bins
+  DevBuf<int2> rb_long;             // intra-task boundary rows, per workgroup
+  DevBuf<int2> rb_resc;
+  DevBuf<int32_t> flags;            // [0] count, [2..] {sid, query} rescoring list
+  DevBuf<uint32_t> prof;            // per-query buffers, grown on demand
+  DevBuf<int8_t> prof2;
+  DevBuf<uint8_t> q_stage;
+  DevBuf<int32_t> out_stage;
   BatchPlan batch;
-  swdb::DevBuf<uint4> rb_batch;    // per-workgroup boundary rows of the batched kernel
-  swdb::DevBuf<int32_t> counter;   // work-queue head of the batched kernel
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  bool use_graphs = true;
-
-  hipStream_t own_stream = nullptr;  // sync API
-  hipStream_t aux_stream = nullptr;  // long-sequence kernel, overlapped
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  DevBuf<uint4> rb_batch;           // per-workgroup boundary rows of the batched kernel
+  DevBuf<int32_t> counter;          // work-queue head of the batched kernel
+  hipStream_t own_stream = nullptr; // host-buffer calls and batch graphs
+  hipStream_t aux_stream = nullptr; // long-sequence kernel, overlapped
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_in = nullptr, ev_out = nullptr;
   // timing: (kind, start, end) event pairs recorded since the last
   // sw_get_stats; events are recycled through `ev_pool`
   struct Timed { int kind; hipEvent_t a, b; };
   std::vector<Timed> timed;
   std::vector<hipEvent_t> ev_pool;
-
   // options
   bool timing = false;
+  bool use_graphs = true;
   int32_t sat_limit = 32767;
   int32_t opt_rows = 0, opt_waves = 0, opt_intra_rows = 0, opt_intra_waves = 0;
-
-  // bookkeeping since the last sw_get_stats
-  sw_stats stats{};
-
+  sw_stats stats{};                 // since the last sw_get_stats
   std::mutex mtx;
+};
+
+}  // namespace swdb
+
+struct sw_db {
+  swdb::DbData data;
+  swdb::Searcher main;
+};
+
+struct sw_ctx {
+  sw_db* owner = nullptr;
+  swdb::Searcher s;
 };
 
 namespace swdb {
 namespace {
 
-void destroy(sw_db* db) {
-  if (!db) return;
-  DeviceGuard g(db->device);
+// Releases a searcher's scratch, streams and events (not the database).
+void release_searcher(Searcher* db) {
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
   if (db->aux_stream) (void)hipStreamSynchronize(db->aux_stream);
-  db->packed.release(); db->bins.release(); db->slot_seq.release(); db->rb.release();
-  db->res.release(); db->offs.release(); db->d_long_items.release(); db->rb_long.release();
-  db->rb_resc.release(); db->flags.release(); db->prof.release(); db->prof2.release();
-  db->q_stage.release(); db->out_stage.release();
+  db->rb.release(); db->rb_long.release(); db->rb_resc.release(); db->flags.release();
+  db->prof.release(); db->prof2.release(); db->q_stage.release(); db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
-  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out})
+  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out}) {
     if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
   for (auto& t : db->timed) { (void)hipEventDestroy(t.a); (void)hipEventDestroy(t.b); }
+  db->timed.clear();
   for (hipEvent_t e : db->ev_pool) (void)hipEventDestroy(e);
+  db->ev_pool.clear();
   if (db->own_stream) (void)hipStreamDestroy(db->own_stream);
   if (db->aux_stream) (void)hipStreamDestroy(db->aux_stream);
-  delete db;
+  db->own_stream = db->aux_stream = nullptr;
 }
 
-int validate_search(const sw_db* db, const void* query, int32_t m, const int8_t* matrix,
+void destroy_db(sw_db* h) {
+  if (!h) return;
+  DeviceGuard g(h->data.device);
+  release_searcher(&h->main);
+  DbData& d = h->data;
+  d.packed.release(); d.bins.release(); d.slot_seq.release(); d.res.release(); d.offs.release();
+  d.d_long_items.release();
+  delete h;
+}
+
+// Makes every buffer of a searcher wait for its streams before reallocation.
+void bind_buffers(Searcher* S) {
+  const StreamSet* u = &S->users;
+  S->rb.users = S->rb_long.users = S->rb_resc.users = u;
+  S->prof.users = u; S->prof2.users = u; S->q_stage.users = u; S->out_stage.users = u;
+  S->rb_batch.users = S->counter.users = S->flags.users = u;
+  BatchPlan& B = S->batch;
+  B.pairs.users = u; B.qdesc.users = u; B.items.users = u; B.long_items.users = u;
+  B.qoffs_d.users = u; B.prof.users = u; B.prof2.users = u;
+}
+
+// Allocates a searcher's fixed scratch, streams and events for database d.
+int init_searcher(Searcher* S, DbData* d) {
+  S->d = d;
+  bind_buffers(S);
+  const Plan& P = d->plan;
+  hipError_t e;
+  if ((e = S->rb.reserve((size_t)P.boundary_uint4)) != hipSuccess ||
+      (e = S->rb_resc.reserve((size_t)kIntraGridRescore * std::max<int32_t>(P.max_all_bin_len, 1))) !=
+          hipSuccess ||
+      (e = S->flags.reserve((size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS, 1)))) !=
+          hipSuccess)
+    return fail(SW_ENOMEM, std::string("search scratch: ") + hipGetErrorString(e));
+  if ((e = hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&S->aux_stream, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e, "stream creation");
+  S->users.set(0, S->own_stream);
+  S->users.set(1, S->aux_stream);
+  S->users.any = true;
+  for (hipEvent_t* ev : {&S->ev_fork, &S->ev_join, &S->ev_in, &S->ev_out})
+    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
+      return hip_fail(e, "event creation");
+  return SW_OK;
+}
+
+int validate_search(const Searcher* db, const void* query, int32_t m, const int8_t* matrix,
                     int32_t go, int32_t ge, const void* out) {
   if (!db) return fail(SW_EINVAL, "db is NULL");
   if (m < 0) return fail(SW_EINVAL, "query_len < 0");
   if (m > SW_MAX_LEN) return fail(SW_ERANGE, "query longer than 2^24-1 residues");
   if (m > 0 && !query) return fail(SW_EINVAL, "query is NULL");
   if (!matrix) return fail(SW_EINVAL, "matrix is NULL");
-  if (db->n_seqs > 0 && !out) return fail(SW_EINVAL, "out_scores is NULL");
+  if (db->d->n_seqs > 0 && !out) return fail(SW_EINVAL, "out_scores is NULL");
   if (ge < 0 || go < ge) return fail(SW_EINVAL, "gaps must satisfy 0 <= gap_extend <= gap_open");
   if (go > SW_MAX_GAP) return fail(SW_ERANGE, "gap_open > 2^30");
   return SW_OK;
 }
 
-int pick_rows(const sw_db* db, int m) {
+int pick_rows(const Searcher* db, int m) {
   if (db->opt_rows) return db->opt_rows;
   const int pad32 = (m + 31) / 32 * 32, pad16 = (m + 15) / 16 * 16;
   return (pad32 - m) * 16 <= (pad16 - m) * 16 + m / 8 ? 32 : 16;  // R=32 unless it pads much more
 }
 
-int pick_waves(const sw_db* db, int n_strips) {
+int pick_waves(const Searcher* db, int n_strips) {
   if (db->opt_waves) return db->opt_waves;
   // more waves per bin shortens each bin's strip pipeline; measured best at 8
   // even when some waves idle in the last round
@@ -211,7 +294,7 @@ int pick_waves(const sw_db* db, int n_strips) {
 // length m: the smallest estimated latency for one long sequence, where a
 // pass of 64R rows costs about (10R + 10) VALU ops per step, waves beyond one
 // per SIMD share it, and the passes run in rounds of W2.
-void pick_intra(const sw_db* db, int m, int max_waves, int* R_out, int* W2_out) {
+void pick_intra(const Searcher* db, int m, int max_waves, int* R_out, int* W2_out) {
   double best = 1e300;
   int bR = 8, bW = 1;
   for (int R : {2, 4, 8}) {
@@ -232,7 +315,7 @@ void pick_intra(const sw_db* db, int m, int max_waves, int* R_out, int* W2_out) 
 
 enum TimedKind { kTimeTotal = 0, kTimeInter = 1, kTimeIntra = 2, kTimeRescore = 3 };
 
-hipEvent_t pool_event(sw_db* db) {
+hipEvent_t pool_event(Searcher* db) {
   if (!db->ev_pool.empty()) {
     hipEvent_t e = db->ev_pool.back();
     db->ev_pool.pop_back();
@@ -245,7 +328,7 @@ hipEvent_t pool_event(sw_db* db) {
 
 // Records the start event of a timed region on stream s (no-op when timing is
 // off); returns the index to close with time_end.
-int time_begin(sw_db* db, int kind, hipStream_t s) {
+int time_begin(Searcher* db, int kind, hipStream_t s) {
   if (!db->timing) return -1;
   hipEvent_t a = pool_event(db), b = pool_event(db);
   if (!a || !b) return -1;
@@ -254,31 +337,31 @@ int time_begin(sw_db* db, int kind, hipStream_t s) {
   return (int)db->timed.size() - 1;
 }
 
-void time_end(sw_db* db, int idx, hipStream_t s) {
+void time_end(Searcher* db, int idx, hipStream_t s) {
   if (idx < 0) return;
   (void)hipEventRecord(db->timed[(size_t)idx].b, s);
 }
 
 // The rescoring list: flags[0] is the count, {sid, query} pairs start at
 // flags + 2 (8-byte aligned).
-int2* flag_list(sw_db* db) { return reinterpret_cast<int2*>(db->flags.p + 2); }
+int2* flag_list(Searcher* db) { return reinterpret_cast<int2*>(db->flags.p + 2); }
 
-hipError_t reserve_flags(sw_db* db, int64_t entries) {
+hipError_t reserve_flags(Searcher* db, int64_t entries) {
   return db->flags.reserve((size_t)(2 + 2 * std::max<int64_t>(entries, 1)));
 }
 
-hipError_t reserve_long_scratch(sw_db* db, int grid) {
+hipError_t reserve_long_scratch(Searcher* db, int grid) {
   return db->rb_long.reserve((size_t)std::max(grid, 1) *
-                             (size_t)std::max<int32_t>(db->plan.max_long_len, 1));
+                             (size_t)std::max<int32_t>(db->d->plan.max_long_len, 1));
 }
 
 // Enqueues one query's search on stream s.  All arguments validated.
-int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
+int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
                    int32_t ge, int32_t* d_out, hipStream_t s) {
   hipError_t e;
-  if (db->n_seqs == 0) return SW_OK;
+  if (db->d->n_seqs == 0) return SW_OK;
   if (m == 0) {
-    e = launch_fill(d_out, db->n_seqs, 0, s);
+    e = launch_fill(d_out, db->d->n_seqs, 0, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "fill");
   }
   const int R = pick_rows(db, m);
@@ -305,8 +388,8 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   // long sequences: intra-task kernel on the auxiliary stream, overlapped
   // with the inter-task bins
   IntraArgs ia{};
-  ia.res = db->res.p;
-  ia.offs = db->offs.p;
+  ia.res = db->d->res.p;
+  ia.offs = db->d->offs.p;
   ia.prof2 = db->prof2.p;
   ia.q0.prof2_off = 0;
   ia.q0.out_off = 0;
@@ -315,20 +398,20 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   ia.go = go;
   ia.ge = ge;
   ia.out = d_out;
-  const int64_t n_long = db->plan.n_long;
+  const int64_t n_long = db->d->plan.n_long;
   if (n_long > 0) {
     if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
       return hip_fail(e, "stream wait");
     IntraArgs la = ia;
-    la.items = db->d_long_items.p;
+    la.items = db->d->d_long_items.p;
     la.count_ptr = nullptr;
     la.count = (int32_t)n_long;
     const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
     if ((e = reserve_long_scratch(db, grid)) != hipSuccess)
       return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
     la.scratch = db->rb_long.p;
-    la.scratch_stride = std::max<int64_t>(db->plan.max_long_len, 1);
+    la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
     la.q0.n_pass = (m + 64 * RR - 1) / (64 * RR);
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
     if ((e = launch_intra(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
@@ -340,8 +423,8 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
 
   // short sequences: inter-task kernel over all bins
   InterArgs a{};
-  a.res2 = reinterpret_cast<const uint2*>(db->packed.p);
-  a.bins = db->bins.p;
+  a.res2 = reinterpret_cast<const uint2*>(db->d->packed.p);
+  a.bins = db->d->bins.p;
   a.bin_begin = 0;
   a.n_strips = n_strips;
   a.prof = db->prof.p;
@@ -350,12 +433,12 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
   a.go2 = go16 | (go16 << 16);
   a.ge2 = ge16 | (ge16 << 16);
   a.rb = db->rb.p;
-  a.slot_seq = db->slot_seq.p;
+  a.slot_seq = db->d->slot_seq.p;
   a.out = d_out;
   a.flag_count = db->flags.p;
   a.flag_list = flag_list(db);
   a.sat_limit = db->sat_limit;
-  const int n_bins = (int)db->plan.n_bins;
+  const int n_bins = (int)db->d->plan.n_bins;
   if (n_bins > 0) {
     const int ti = time_begin(db, kTimeInter, s);
     if ((e = launch_inter(R, W, n_bins, a, s)) != hipSuccess) return hip_fail(e, "inter-task kernel");
@@ -367,7 +450,7 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
     ra.count_ptr = db->flags.p;
     ra.count = 0;
     ra.scratch = db->rb_resc.p;
-    ra.scratch_stride = std::max<int64_t>(db->plan.max_bin_len, 1);
+    ra.scratch_stride = std::max<int64_t>(db->d->plan.max_bin_len, 1);
     ra.q0.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
     const int tr = time_begin(db, kTimeRescore, s);
     if ((e = launch_intra(RRr, W2r, kIntraGridRescore, ra, s)) != hipSuccess)
@@ -380,8 +463,8 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
 
   db->stats.rows = R;
   db->stats.waves = W;
-  const int64_t long_res = db->long_residues;
-  db->stats.inter_cells += (int64_t)m * (db->n_res - long_res);
+  const int64_t long_res = db->d->long_residues;
+  db->stats.inter_cells += (int64_t)m * (db->d->n_res - long_res);
   db->stats.intra_cells += (int64_t)m * long_res;
   return SW_OK;
 }
@@ -390,7 +473,7 @@ int enqueue_search(sw_db* db, const uint8_t* d_query, int32_t m, const Matrix& m
 // buffers: pairs of length-sorted queries, pair and per-query descriptors,
 // the (pair, half bin) work list costliest first, and the (sequence, query)
 // list of long-sequence items.
-int prepare_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
+int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
                   const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out) {
   BatchPlan& B = db->batch;
   const int R = db->opt_rows ? db->opt_rows : 32;
@@ -438,37 +521,40 @@ int prepare_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int
     qd[q].m_pad2 = (int32_t)((m + 511) / 512 * 512);
     qd[q].n_pass = (int32_t)((m + 64 * RR - 1) / (64 * RR));
     qd[q].prof2_off = prof2_bytes;
-    qd[q].out_off = (int64_t)q * db->n_seqs;
+    qd[q].out_off = (int64_t)q * db->d->n_seqs;
     prof2_bytes += (int64_t)kIntraCodes * qd[q].m_pad2;
     if (ms[q] > 0) B.max_query_work = std::max<int64_t>(B.max_query_work, (int64_t)kIntraCodes * qd[q].m_pad2);
   }
   // (pair, half bin) items, costliest first
-  const int64_t n_hb = 2 * db->plan.n_bins;
+  // every half bin holding at least one sequence, short and long bins
+  const int64_t n_hb = 2 * (db->d->plan.n_bins + db->d->plan.n_long_bins);
   std::vector<int2> items;
   items.reserve((size_t)(n_hb * (int64_t)pairs.size()));
-  for (int64_t hb = 0; hb < n_hb; ++hb)
+  for (int64_t hb = 0; hb < n_hb; ++hb) {
+    if (db->d->plan.bin_count[(size_t)(hb >> 1)] <= (hb & 1)) continue;
     for (int p = 0; p < (int)pairs.size(); ++p) items.push_back(make_int2(p, (int)hb));
-  const std::vector<int64_t>& bins = db->plan.bins;
+  }
+  const std::vector<int64_t>& bins = db->d->plan.bins;
   auto cost = [&](const int2& it) {
     return (int64_t)pairs[it.x].n_strips * (bins[(size_t)(it.y >> 1) * 4 + 2] / 4 + 2 * W);
   };
   std::stable_sort(items.begin(), items.end(),
                    [&](const int2& a, const int2& b) { return cost(a) > cost(b); });
-  // (long sequence, query) items, costliest first
+  // (very long sequence, query) items, costliest first
   std::vector<int2> litems;
-  for (int64_t t = 0; t < db->plan.n_long; ++t)
-    for (int32_t q : order) litems.push_back(make_int2(db->long_ids[(size_t)t], q));
+  for (int64_t t = 0; t < db->d->plan.n_vlong; ++t)
+    for (int32_t q : order) litems.push_back(make_int2(db->d->long_ids[(size_t)t], q));
   const int64_t* offs = nullptr;
   (void)offs;
   auto lcost = [&](const int2& it) {
-    return ms[it.y] * (int64_t)db->long_len[(size_t)it.x];
+    return ms[it.y] * (int64_t)db->d->long_len[(size_t)it.x];
   };
   std::stable_sort(litems.begin(), litems.end(),
                    [&](const int2& a, const int2& b) { return lcost(a) > lcost(b); });
   B.inter_cells = B.intra_cells = 0;
   for (int32_t q : order) {
-    B.inter_cells += ms[q] * (db->n_res - db->long_residues);
-    B.intra_cells += ms[q] * db->long_residues;
+    B.inter_cells += ms[q] * (db->d->n_res - db->d->vlong_residues);
+    B.intra_cells += ms[q] * db->d->vlong_residues;
   }
 
   auto put = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
@@ -496,11 +582,13 @@ int prepare_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int
   B.RR = RR;
   B.W2 = W2;
   B.W2r = W2r;
-  B.grid_b = db->n_cus * batch_workgroups_per_cu(R, W);
+  B.grid_b = db->d->n_cus * batch_workgroups_per_cu(R, W);
   B.grid_long = (int)std::min<int64_t>(B.n_long_items, kIntraGridLong);
-  if ((e = db->rb_batch.reserve((size_t)B.grid_b * (size_t)(db->plan.max_bin_len / 4) * 128)) != hipSuccess ||
+  if ((e = db->rb_batch.reserve((size_t)B.grid_b * (size_t)(db->d->plan.max_all_bin_len / 4) * 128)) !=
+          hipSuccess ||
       (e = db->counter.reserve(1)) != hipSuccess ||
-      (e = reserve_flags(db, (db->plan.n_bins * (int64_t)SW_BIN_SEQS) * std::max(n_nz, 1))) != hipSuccess ||
+      (e = reserve_flags(db, ((db->d->plan.n_bins + db->d->plan.n_long_bins) * (int64_t)SW_BIN_SEQS) *
+                                 std::max(n_nz, 1))) != hipSuccess ||
       (e = reserve_long_scratch(db, std::max(B.grid_long, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("batch scratch: ") + hipGetErrorString(e));
   B.qoffs = qv;
@@ -515,10 +603,10 @@ int prepare_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int
 }
 
 // Enqueues the prepared batch on stream s (graph capture safe: kernels only).
-int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
+int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
   BatchPlan& B = db->batch;
   hipError_t e;
-  const int64_t n = db->n_seqs;
+  const int64_t n = db->d->n_seqs;
   const int t_total = time_begin(db, kTimeTotal, s);
   if ((e = launch_fill(db->counter.p, 1, 0, s)) != hipSuccess ||
       (e = launch_fill(db->flags.p, 1, 0, s)) != hipSuccess)
@@ -535,32 +623,31 @@ int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
                                  B.prof2.p, s)) != hipSuccess)
     return hip_fail(e, "batch profiles");
   IntraArgs ia{};
-  ia.res = db->res.p;
-  ia.offs = db->offs.p;
+  ia.res = db->d->res.p;
+  ia.offs = db->d->offs.p;
   ia.prof2 = B.prof2.p;
   ia.queries = B.qdesc.p;
   ia.go = B.go;
   ia.ge = B.ge;
   ia.out = B.d_out;
+  // Very long sequences first, on the same stream: the persistent batched
+  // kernel holds every CU until its list is drained, so a concurrent launch
+  // would only get CUs at the end.  These items are few and run in parallel.
   if (B.n_long_items > 0) {
-    if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
-      return hip_fail(e, "stream wait");
     IntraArgs la = ia;
     la.items = B.long_items.p;
     la.count = (int32_t)B.n_long_items;
     la.scratch = db->rb_long.p;
-    la.scratch_stride = std::max<int64_t>(db->plan.max_long_len, 1);
-    const int tl = time_begin(db, kTimeIntra, db->aux_stream);
-    if ((e = launch_intra(B.RR, B.W2, B.grid_long, la, db->aux_stream)) != hipSuccess)
+    la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
+    const int tl = time_begin(db, kTimeIntra, s);
+    if ((e = launch_intra(B.RR, B.W2, B.grid_long, la, s)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
-    time_end(db, tl, db->aux_stream);
-    if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess) return hip_fail(e, "event");
+    time_end(db, tl, s);
   }
-  if (db->plan.n_bins > 0) {
+  if (db->d->plan.n_bins + db->d->plan.n_long_bins > 0) {
     BatchArgs ba{};
-    ba.res = db->packed.p;
-    ba.bins = db->bins.p;
+    ba.res = db->d->packed.p;
+    ba.bins = db->d->bins.p;
     ba.items = B.items.p;
     ba.n_items = (int32_t)B.n_items;
     ba.counter = db->counter.p;
@@ -571,8 +658,8 @@ int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
     ba.go2 = go16 | (go16 << 16);
     ba.ge2 = ge16 | (ge16 << 16);
     ba.rb = db->rb_batch.p;
-    ba.rb_stride = (int64_t)(db->plan.max_bin_len / 4) * 128;
-    ba.slot_seq = db->slot_seq.p;
+    ba.rb_stride = (int64_t)(db->d->plan.max_all_bin_len / 4) * 128;
+    ba.slot_seq = db->d->slot_seq.p;
     ba.out = B.d_out;
     ba.n_seqs = n;
     ba.flag_count = db->flags.p;
@@ -586,14 +673,12 @@ int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
     ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;
     ra.scratch = db->rb_resc.p;
-    ra.scratch_stride = std::max<int64_t>(db->plan.max_bin_len, 1);
+    ra.scratch_stride = std::max<int64_t>(db->d->plan.max_all_bin_len, 1);
     const int tr = time_begin(db, kTimeRescore, s);
     if ((e = launch_intra(B.RR, B.W2r, kIntraGridRescore, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
     time_end(db, tr, s);
   }
-  if (B.n_long_items > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
-    return hip_fail(e, "stream wait");
   time_end(db, t_total, s);
   return SW_OK;
 }
@@ -601,10 +686,10 @@ int enqueue_batch_kernels(sw_db* db, hipStream_t s) {
 // Runs a batch: the kernels are captured once into a HIP graph on the
 // handle's own stream and replayed while the plan stays the same; the
 // caller's stream is ordered before and after with events.
-int run_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
+int run_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
               const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out, hipStream_t s) {
   hipError_t e;
-  if (db->n_seqs == 0 || nq == 0) return SW_OK;
+  if (db->d->n_seqs == 0 || nq == 0) return SW_OK;
   int rc = prepare_batch(db, d_queries, qoffs, nq, mat, go, ge, d_out);
   if (rc != SW_OK) return rc;
   BatchPlan& B = db->batch;
@@ -637,7 +722,7 @@ int run_batch(sw_db* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t
     return hip_fail(e, "stream order");
   db->stats.rows = B.R;
   db->stats.waves = B.W;
-  db->stats.n_inter_launches += db->plan.n_bins > 0 ? 1 : 0;
+  db->stats.n_inter_launches += db->d->plan.n_bins + db->d->plan.n_long_bins > 0 ? 1 : 0;
   db->stats.inter_cells += B.inter_cells;
   db->stats.intra_cells += B.intra_cells;
   return SW_OK;
@@ -653,24 +738,33 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   using namespace swdb;
   if (!out_db) return fail(SW_EINVAL, "out_db is NULL");
   *out_db = nullptr;
-  sw_db* db = new (std::nothrow) sw_db();
-  if (!db) return fail(SW_ENOMEM, "host allocation failed");
-  db->plan.check_codes = true;
-  int rc = plan_layout(residues, offsets, n_seqs, long_threshold, &db->plan);
-  if (rc != SW_OK) { delete db; return rc; }
-  hipError_t e = hipGetDevice(&db->device);
-  if (e != hipSuccess) { delete db; return hip_fail(e, "no HIP device"); }
-  DeviceGuard g(db->device);
-  db->n_seqs = n_seqs;
-  db->n_res = offsets[n_seqs];
-  const Plan& P = db->plan;
-  db->long_ids.resize((size_t)P.n_long);
-  db->long_len.assign((size_t)std::max<int64_t>(n_seqs, 1), 0);
+  sw_db* h = new (std::nothrow) sw_db();
+  if (!h) return fail(SW_ENOMEM, "host allocation failed");
+  DbData* d = &h->data;
+  d->plan.check_codes = true;
+  int rc = plan_layout(residues, offsets, n_seqs, long_threshold, &d->plan);
+  if (rc != SW_OK) { delete h; return rc; }
+  hipError_t e = hipGetDevice(&d->device);
+  if (e != hipSuccess) { delete h; return hip_fail(e, "no HIP device"); }
+  DeviceGuard g(d->device);
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, d->device) == hipSuccess &&
+        ncu > 0)
+      d->n_cus = ncu;
+  }
+  d->n_seqs = n_seqs;
+  d->n_res = offsets[n_seqs];
+  const Plan& P = d->plan;
+  d->long_ids.resize((size_t)P.n_long);
+  d->long_len.assign((size_t)std::max<int64_t>(n_seqs, 1), 0);
   for (int64_t t = 0; t < P.n_long; ++t) {
-    db->long_len[(size_t)P.order[(size_t)t]] =
-        (int32_t)(offsets[P.order[(size_t)t] + 1] - offsets[P.order[(size_t)t]]);
-    db->long_ids[(size_t)t] = P.order[(size_t)t];
-    db->long_residues += offsets[P.order[(size_t)t] + 1] - offsets[P.order[(size_t)t]];
+    const int32_t sid = P.order[(size_t)t];
+    const int64_t len = offsets[sid + 1] - offsets[sid];
+    d->long_len[(size_t)sid] = (int32_t)len;
+    d->long_ids[(size_t)t] = sid;
+    d->long_residues += len;
+    if (t < P.n_vlong) d->vlong_residues += len;
   }
   // host staging of the interleaved store
   std::vector<uint32_t> h_packed;
@@ -678,11 +772,11 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   std::vector<int32_t> h_slots, h_long;
   try {
     h_packed.resize((size_t)P.packed_dwords);
-    h_bins.resize((size_t)P.n_bins * 4);
-    h_slots.resize((size_t)P.n_bins * SW_BIN_SEQS);
+    h_bins.resize((size_t)(P.n_bins + P.n_long_bins) * 4);
+    h_slots.resize((size_t)(P.n_bins + P.n_long_bins) * SW_BIN_SEQS);
     h_long.resize((size_t)P.n_long);
   } catch (...) {
-    destroy(db);
+    destroy_db(h);
     return fail(SW_ENOMEM, "host staging allocation failed");
   }
   fill_layout(residues, offsets, P, h_packed.data(), h_bins.data(), h_slots.data(), h_long.data());
@@ -690,52 +784,36 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   for (size_t t = 0; t < h_long.size(); ++t) h_long_items[t] = make_int2(h_long[t], 0);
 
   auto alloc_fail = [&](hipError_t err, const char* what) {
-    destroy(db);
+    destroy_db(h);
     return fail(SW_ENOMEM, std::string(what) + ": " + hipGetErrorString(err));
   };
-  if ((e = db->packed.reserve((size_t)P.packed_dwords)) != hipSuccess) return alloc_fail(e, "packed");
-  if ((e = db->bins.reserve((size_t)P.n_bins)) != hipSuccess) return alloc_fail(e, "bins");
-  if ((e = db->slot_seq.reserve(h_slots.size())) != hipSuccess) return alloc_fail(e, "slots");
-  if ((e = db->rb.reserve((size_t)P.boundary_uint4)) != hipSuccess) return alloc_fail(e, "boundary");
-  if ((e = db->res.reserve((size_t)db->n_res)) != hipSuccess) return alloc_fail(e, "residues");
-  if ((e = db->offs.reserve((size_t)n_seqs + 1)) != hipSuccess) return alloc_fail(e, "offsets");
-  if ((e = db->d_long_items.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
-  if ((e = db->rb_resc.reserve((size_t)kIntraGridRescore * std::max<int32_t>(P.max_bin_len, 1))) !=
-      hipSuccess)
-    return alloc_fail(e, "rescore scratch");
-  if ((e = reserve_flags(db, (int64_t)P.n_bins * SW_BIN_SEQS)) != hipSuccess)
-    return alloc_fail(e, "flags");
-
+  if ((e = d->packed.reserve((size_t)P.packed_dwords)) != hipSuccess) return alloc_fail(e, "packed");
+  if ((e = d->bins.reserve((size_t)(P.n_bins + P.n_long_bins))) != hipSuccess)
+    return alloc_fail(e, "bins");
+  if ((e = d->slot_seq.reserve(h_slots.size())) != hipSuccess) return alloc_fail(e, "slots");
+  if ((e = d->res.reserve((size_t)d->n_res)) != hipSuccess) return alloc_fail(e, "residues");
+  if ((e = d->offs.reserve((size_t)n_seqs + 1)) != hipSuccess) return alloc_fail(e, "offsets");
+  if ((e = d->d_long_items.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
   };
-  if ((e = up(db->packed.p, h_packed.data(), h_packed.size() * 4)) != hipSuccess ||
-      (e = up(db->bins.p, h_bins.data(), h_bins.size() * 8)) != hipSuccess ||
-      (e = up(db->slot_seq.p, h_slots.data(), h_slots.size() * 4)) != hipSuccess ||
-      (e = up(db->res.p, residues, (size_t)db->n_res)) != hipSuccess ||
-      (e = up(db->offs.p, offsets, ((size_t)n_seqs + 1) * 8)) != hipSuccess ||
-      (e = up(db->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess) {
-    destroy(db);
+  if ((e = up(d->packed.p, h_packed.data(), h_packed.size() * 4)) != hipSuccess ||
+      (e = up(d->bins.p, h_bins.data(), h_bins.size() * 8)) != hipSuccess ||
+      (e = up(d->slot_seq.p, h_slots.data(), h_slots.size() * 4)) != hipSuccess ||
+      (e = up(d->res.p, residues, (size_t)d->n_res)) != hipSuccess ||
+      (e = up(d->offs.p, offsets, ((size_t)n_seqs + 1) * 8)) != hipSuccess ||
+      (e = up(d->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess) {
+    destroy_db(h);
     return hip_fail(e, "database upload");
   }
-  if ((e = hipStreamCreateWithFlags(&db->own_stream, hipStreamNonBlocking)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&db->aux_stream, hipStreamNonBlocking)) != hipSuccess) {
-    destroy(db);
-    return hip_fail(e, "stream creation");
+  if ((rc = init_searcher(&h->main, d)) != SW_OK) {
+    std::string msg = get_error();
+    destroy_db(h);
+    set_error(msg);
+    return rc;
   }
-  {
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, db->device) == hipSuccess &&
-        ncu > 0)
-      db->n_cus = ncu;
-  }
-  for (hipEvent_t* ev : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out})
-    if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess) {
-      destroy(db);
-      return hip_fail(e, "event creation");
-    }
-  *out_db = db;
+  *out_db = h;
   set_error("");
   return SW_OK;
 }
@@ -744,19 +822,20 @@ int sw_db_load(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs, 
   return sw_db_load_ex(residues, offsets, n_seqs, 0, out_db);
 }
 
-void sw_db_free(sw_db* db) { swdb::destroy(db); }
+void sw_db_free(sw_db* h) { swdb::destroy_db(h); }
 
-int sw_db_info(const sw_db* db, int64_t* n_seqs, int64_t* n_residues, int32_t* max_len,
+int sw_db_info(const sw_db* h, int64_t* n_seqs, int64_t* n_residues, int32_t* max_len,
                int64_t* n_long) {
-  if (!db) return swdb::fail(SW_EINVAL, "db is NULL");
-  if (n_seqs) *n_seqs = db->n_seqs;
-  if (n_residues) *n_residues = db->n_res;
-  if (max_len) *max_len = db->plan.max_len;
-  if (n_long) *n_long = db->plan.n_long;
+  if (!h) return swdb::fail(SW_EINVAL, "db is NULL");
+  const swdb::DbData* d = &h->data;
+  if (n_seqs) *n_seqs = d->n_seqs;
+  if (n_residues) *n_residues = d->n_res;
+  if (max_len) *max_len = d->plan.max_len;
+  if (n_long) *n_long = d->plan.n_long;
   return SW_OK;
 }
 
-int sw_search_async(sw_db* db, const uint8_t* d_query, int32_t query_len, const int8_t* matrix,
+static int impl_search_async(swdb::Searcher* db, const uint8_t* d_query, int32_t query_len, const int8_t* matrix,
                     int32_t gap_open, int32_t gap_extend, int32_t* d_out_scores,
                     void* hip_stream) {
   using namespace swdb;
@@ -764,16 +843,17 @@ int sw_search_async(sw_db* db, const uint8_t* d_query, int32_t query_len, const 
   if (rc != SW_OK) return rc;
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
-  DeviceGuard g(db->device);
+  DeviceGuard g(db->d->device);
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
+  db->users.set(2, reinterpret_cast<hipStream_t>(hip_stream));
   rc = enqueue_search(db, d_query, query_len, mat, gap_open, gap_extend, d_out_scores,
                       reinterpret_cast<hipStream_t>(hip_stream));
   if (rc == SW_OK) set_error("");
   return rc;
 }
 
-int sw_search(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+static int impl_search(swdb::Searcher* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
               int32_t gap_open, int32_t gap_extend, int32_t* out_scores) {
   using namespace swdb;
   int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, out_scores);
@@ -782,10 +862,10 @@ int sw_search(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* 
     if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
-  DeviceGuard g(db->device);
+  DeviceGuard g(db->d->device);
   hipError_t e;
   if ((e = db->q_stage.reserve((size_t)std::max(query_len, 1))) != hipSuccess ||
-      (e = db->out_stage.reserve((size_t)std::max<int64_t>(db->n_seqs, 1))) != hipSuccess)
+      (e = db->out_stage.reserve((size_t)std::max<int64_t>(db->d->n_seqs, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
   hipStream_t s = db->own_stream;
   if (query_len > 0 &&
@@ -799,8 +879,8 @@ int sw_search(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* 
     (void)hipStreamSynchronize(s);
     return rc;
   }
-  if (db->n_seqs > 0 &&
-      (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)db->n_seqs * 4, hipMemcpyDeviceToHost,
+  if (db->d->n_seqs > 0 &&
+      (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)db->d->n_seqs * 4, hipMemcpyDeviceToHost,
                           s)) != hipSuccess)
     return hip_fail(e, "score download");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
@@ -808,7 +888,7 @@ int sw_search(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* 
   return SW_OK;
 }
 
-static int validate_batch(const sw_db* db, const void* queries, const int64_t* qoffs, int32_t nq,
+static int validate_batch(const swdb::Searcher* db, const void* queries, const int64_t* qoffs, int32_t nq,
                           const int8_t* matrix, int32_t go, int32_t ge, const void* out) {
   using namespace swdb;
   if (!db) return fail(SW_EINVAL, "db is NULL");
@@ -822,13 +902,13 @@ static int validate_batch(const sw_db* db, const void* queries, const int64_t* q
   }
   if (nq > 0 && qoffs[nq] > 0 && !queries) return fail(SW_EINVAL, "queries is NULL");
   if (!matrix) return fail(SW_EINVAL, "matrix is NULL");
-  if (nq > 0 && db->n_seqs > 0 && !out) return fail(SW_EINVAL, "out_scores is NULL");
+  if (nq > 0 && db->d->n_seqs > 0 && !out) return fail(SW_EINVAL, "out_scores is NULL");
   if (ge < 0 || go < ge) return fail(SW_EINVAL, "gaps must satisfy 0 <= gap_extend <= gap_open");
   if (go > SW_MAX_GAP) return fail(SW_ERANGE, "gap_open > 2^30");
   return SW_OK;
 }
 
-int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* query_offsets,
+static int impl_search_batch_async(swdb::Searcher* db, const uint8_t* d_queries, const int64_t* query_offsets,
                           int32_t n_queries, const int8_t* matrix, int32_t gap_open,
                           int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
   using namespace swdb;
@@ -837,16 +917,17 @@ int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* qu
   if (rc != SW_OK) return rc;
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
-  DeviceGuard g(db->device);
+  DeviceGuard g(db->d->device);
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
+  db->users.set(2, reinterpret_cast<hipStream_t>(hip_stream));
   rc = run_batch(db, d_queries, query_offsets, n_queries, mat, gap_open, gap_extend, d_out_scores,
                  reinterpret_cast<hipStream_t>(hip_stream));
   if (rc == SW_OK) set_error("");
   return rc;
 }
 
-int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offsets,
+static int impl_search_batch(swdb::Searcher* db, const uint8_t* queries, const int64_t* query_offsets,
                     int32_t n_queries, const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
                     int32_t* out_scores) {
   using namespace swdb;
@@ -858,10 +939,10 @@ int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offs
     if (queries[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
-  DeviceGuard g(db->device);
+  DeviceGuard g(db->d->device);
   hipError_t e;
   hipStream_t s = db->own_stream;
-  const size_t out_n = (size_t)n_queries * (size_t)db->n_seqs;
+  const size_t out_n = (size_t)n_queries * (size_t)db->d->n_seqs;
   if ((e = db->q_stage.reserve((size_t)std::max<int64_t>(total, 1))) != hipSuccess ||
       (e = db->out_stage.reserve(std::max<size_t>(out_n, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
@@ -882,7 +963,7 @@ int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offs
   return SW_OK;
 }
 
-int sw_set_option(sw_db* db, int32_t key, int64_t value) {
+static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
   using namespace swdb;
   if (!db) return fail(SW_EINVAL, "db is NULL");
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
@@ -925,12 +1006,12 @@ int sw_set_option(sw_db* db, int32_t key, int64_t value) {
   }
 }
 
-int sw_get_stats(sw_db* db, sw_stats* out) {
+static int impl_get_stats(swdb::Searcher* db, sw_stats* out) {
   using namespace swdb;
   if (!db || !out) return fail(SW_EINVAL, "NULL argument");
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
-  DeviceGuard g(db->device);
+  DeviceGuard g(db->d->device);
   sw_stats st = db->stats;
   hipError_t e;
   hipEvent_t first = nullptr, last = nullptr;
@@ -952,7 +1033,7 @@ int sw_get_stats(sw_db* db, sw_stats* out) {
   db->timed.clear();
   int32_t cnt = 0;
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
-  if (db->flags.p && db->plan.n_bins > 0) {
+  if (db->flags.p && db->d->plan.n_bins > 0) {
     if ((e = hipMemcpy(&cnt, db->flags.p, 4, hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "stats");
   }
@@ -961,5 +1042,101 @@ int sw_get_stats(sw_db* db, sw_stats* out) {
   db->stats = sw_stats{};
   return SW_OK;
 }
+
+// ------------------------------------------------------------ public entry
+// points: a database handle searches with its own searcher, a context with
+// its private one.
+static swdb::Searcher* S_of(sw_db* h) { return h ? &h->main : nullptr; }
+static swdb::Searcher* S_of(sw_ctx* c) { return c ? &c->s : nullptr; }
+
+int sw_search(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+              int32_t gap_open, int32_t gap_extend, int32_t* out_scores) {
+  return impl_search(S_of(h), query, query_len, matrix, gap_open, gap_extend, out_scores);
+}
+int sw_search_async(sw_db* h, const uint8_t* d_query, int32_t query_len, const int8_t* matrix,
+                    int32_t gap_open, int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_async(S_of(h), d_query, query_len, matrix, gap_open, gap_extend, d_out_scores,
+                           hip_stream);
+}
+int sw_search_batch(sw_db* h, const uint8_t* queries, const int64_t* query_offsets,
+                    int32_t n_queries, const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                    int32_t* out_scores) {
+  return impl_search_batch(S_of(h), queries, query_offsets, n_queries, matrix, gap_open,
+                           gap_extend, out_scores);
+}
+int sw_search_batch_async(sw_db* h, const uint8_t* d_queries, const int64_t* query_offsets,
+                          int32_t n_queries, const int8_t* matrix, int32_t gap_open,
+                          int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_batch_async(S_of(h), d_queries, query_offsets, n_queries, matrix, gap_open,
+                                 gap_extend, d_out_scores, hip_stream);
+}
+int sw_set_option(sw_db* h, int32_t key, int64_t value) {
+  return impl_set_option(S_of(h), key, value);
+}
+int sw_get_stats(sw_db* h, sw_stats* out) { return impl_get_stats(S_of(h), out); }
+
+int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
+  using namespace swdb;
+  if (!out_ctx) return fail(SW_EINVAL, "out_ctx is NULL");
+  *out_ctx = nullptr;
+  if (!h) return fail(SW_EINVAL, "db is NULL");
+  sw_ctx* c = new (std::nothrow) sw_ctx();
+  if (!c) return fail(SW_ENOMEM, "host allocation failed");
+  c->owner = h;
+  DeviceGuard g(h->data.device);
+  int rc = init_searcher(&c->s, &h->data);
+  if (rc != SW_OK) {
+    std::string msg = get_error();
+    release_searcher(&c->s);
+    delete c;
+    set_error(msg);
+    return rc;
+  }
+  {  // options start as the database handle's
+    std::lock_guard<std::mutex> lk(h->main.mtx);
+    c->s.timing = h->main.timing;
+    c->s.use_graphs = h->main.use_graphs;
+    c->s.sat_limit = h->main.sat_limit;
+    c->s.opt_rows = h->main.opt_rows;
+    c->s.opt_waves = h->main.opt_waves;
+    c->s.opt_intra_rows = h->main.opt_intra_rows;
+    c->s.opt_intra_waves = h->main.opt_intra_waves;
+  }
+  *out_ctx = c;
+  set_error("");
+  return SW_OK;
+}
+
+void sw_ctx_free(sw_ctx* c) {
+  if (!c) return;
+  swdb::DeviceGuard g(c->owner->data.device);
+  swdb::release_searcher(&c->s);
+  delete c;
+}
+
+int64_t sw_ctx_bytes(const sw_db* h) {
+  if (!h) return -1;
+  const swdb::Plan& P = h->data.plan;
+  return P.boundary_uint4 * 16 +
+         (int64_t)swdb::kIntraGridRescore * std::max<int32_t>(P.max_all_bin_len, 1) * 8 +
+         (2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS, 1)) * 4;
+}
+
+int sw_ctx_search_async(sw_ctx* c, const uint8_t* d_query, int32_t query_len,
+                        const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                        int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_async(S_of(c), d_query, query_len, matrix, gap_open, gap_extend,
+                           d_out_scores, hip_stream);
+}
+int sw_ctx_search_batch_async(sw_ctx* c, const uint8_t* d_queries, const int64_t* query_offsets,
+                              int32_t n_queries, const int8_t* matrix, int32_t gap_open,
+                              int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_batch_async(S_of(c), d_queries, query_offsets, n_queries, matrix, gap_open,
+                                 gap_extend, d_out_scores, hip_stream);
+}
+int sw_ctx_set_option(sw_ctx* c, int32_t key, int64_t value) {
+  return impl_set_option(S_of(c), key, value);
+}
+int sw_ctx_get_stats(sw_ctx* c, sw_stats* out) { return impl_get_stats(S_of(c), out); }
 
 }  // extern "C"

@@ -39,7 +39,7 @@ def _unpack(p, offsets):
     return seqs
 
 
-@pytest.mark.parametrize("t_long", [0, 1, 50, 400, 10**6])
+@pytest.mark.parametrize("t_long", [0, 1, 50, 100, 400, 10**6])
 def test_pack_roundtrip(t_long):
     rng = np.random.default_rng(3)
     lengths = np.concatenate([rng.integers(0, 600, 700), [0, 0, 1, 2, 3, 4, 5, 1000, 2500]])
@@ -51,20 +51,30 @@ def test_pack_roundtrip(t_long):
     assert info["long_threshold"] == thr
     seqs = _unpack(p, offs)
     long_ids = p["long_ids"].tolist()
-    # every sequence appears exactly once, long ones in the long list
-    assert sorted(list(seqs.keys()) + long_ids) == list(range(len(lengths)))
+    vthr = info["very_long_threshold"]
+    assert vthr == 4 * thr
+    nb = info["n_bins"]
+    short_ids = [s for s in p["slot_seq"][:nb * sw.SW_BIN_SEQS].tolist() if s >= 0]
+    binned_long = [s for s in p["slot_seq"][nb * sw.SW_BIN_SEQS:].tolist() if s >= 0]
+    # every sequence is in exactly one short bin or in the long list
+    assert sorted(short_ids + long_ids) == list(range(len(lengths)))
     for sid, codes in seqs.items():
         assert (codes == res[offs[sid]:offs[sid + 1]]).all()
+    for sid in short_ids:
         assert lengths[sid] < thr
     for sid in long_ids:
         assert lengths[sid] >= thr
+    # the long bins hold exactly the long sequences below the very-long cut
+    assert sorted(binned_long) == sorted(s for s in long_ids if lengths[s] < vthr)
+    assert info["n_very_long"] == sum(1 for s in long_ids if lengths[s] >= vthr)
+    assert long_ids[:info["n_very_long"]] == [s for s in long_ids if lengths[s] >= vthr]
     # long list longest first, ties by index
     ll = [(-lengths[s], s) for s in long_ids]
     assert ll == sorted(ll)
     # bins hold length-sorted slots (stable), bin length = padded first length
-    order = [s for s in p["slot_seq"].tolist() if s >= 0]
-    key = [(-lengths[s], s) for s in order]
-    assert key == sorted(key)
+    for part in (short_ids, binned_long):
+        key = [(-lengths[s], s) for s in part]
+        assert key == sorted(key)
     for res_off, rb_off, blen, slot0 in p["bins"]:
         first = p["slot_seq"][slot0]
         assert blen == max(sw.SW_MIN_BIN_LEN, (lengths[first] + 3) // 4 * 4)
