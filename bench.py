@@ -4,9 +4,17 @@ One step = the paper's search protocol on the full synthetic stand-in
 workload: 20 queries (lengths 144..5478) each searched against the resident
 200,000-sequence database (71M residues), BLOSUM62, gaps 10/2, one search
 (profile + inter-task + intra-task + rescoring kernels) per query.  GCUPS =
-sum over queries of m * N / time (paper section 4.2).
+sum over queries of m * N / time (paper section 4.2).  This plain form is the
+headline `value`.
+
+Beside it, on the same resident database:
+  batched : the 20 queries + 200 of length U[50, 5000] in one batched search
+            (paired-query persistent kernel, replayed from a HIP graph)
+  served  : Poisson arrivals (50 QPS, lengths log-normal, median 400) through
+            the continuous-batching server; p50/p99 latency and GCUPS
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-batched] [--no-served] [--requests N] [--qps Q]
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -59,6 +67,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--requests", type=int, default=2000)
+    ap.add_argument("--qps", type=float, default=50.0)
     ap.add_argument("--scale", type=float, default=1.0, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -128,11 +140,61 @@ def main():
         "kernel_ms_per_step": {k: st[k] / args.steps for k in
                                ("ms_inter", "ms_intra", "ms_rescore")},
     }
+    if not args.no_batched:
+        result["batched"] = batched_leg(db, args.scale)
+    if not args.no_served:
+        result["served"] = served_leg(db, args.scale, args.requests, args.qps)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(w)
     db.close()
     print(json.dumps(result), flush=True)
+
+
+def batched_leg(db, scale):
+    """220 queries in one batched search; first call plans and captures the
+    graph (untimed), then one timed replay."""
+    import numpy as np
+    import torch
+    import swinputs
+    wb = swinputs.config("batched", scale=scale)
+    cells = wb.cells()
+    log("batched: %d queries, %.3e cells" % (len(wb.queries), cells))
+    cat = torch.from_numpy(np.concatenate(wb.queries)).cuda()
+    qoffs = np.zeros(len(wb.queries) + 1, np.int64)
+    np.cumsum([len(q) for q in wb.queries], out=qoffs[1:])
+    out = torch.empty((len(wb.queries), db.n_seqs), dtype=torch.int32, device="cuda")
+    db.search_batch_async(cat, qoffs, wb.matrix, wb.gap_open, wb.gap_extend, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    db.search_batch_async(cat, qoffs, wb.matrix, wb.gap_open, wb.gap_extend, out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    db.stats()
+    del out
+    log("batched: %.3f s, %.0f GCUPS" % (dt, cells / dt / 1e9))
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "ms_per_step": dt * 1e3,
+            "n_queries": len(wb.queries), "cells_per_step": cells,
+            "form": "one batched search (paired queries, persistent kernel, HIP graph replay)"}
+
+
+def served_leg(db, scale, n_requests, qps, slots=4, max_batch=8):
+    import numpy as np
+    import swinputs
+    from paper_2203_11100_amd import serve
+    ws = swinputs.config("served", scale=scale, n_requests=n_requests, qps=qps)
+    srv = serve.Server(db, ws.matrix, ws.gap_open, ws.gap_extend, max_slots=slots,
+                       max_batch=max_batch, max_query_len=5000)
+    srv.ex.warm()
+    log("served: %d requests at %.0f QPS on %d slots ..." % (n_requests, qps, srv.n_slots))
+    reqs = srv.run(ws.queries, ws.arrivals)
+    srv.close()
+    s = serve.summarize(reqs, ws.n_residues)
+    log("served: %s" % s)
+    s.update({"qps": qps, "slots": srv.n_slots, "max_batch": max_batch, "unit_latency": "ms",
+              "arrivals": "Poisson, query lengths log-normal (median 400, sigma 0.8, "
+                          "clip 30..5000)"})
+    return s
 
 
 if __name__ == "__main__":

@@ -181,6 +181,29 @@ typedef struct sw_stats {
 /* Waits for the recorded work, fills *out and resets the counters. */
 int sw_get_stats(sw_db* db, sw_stats* out);
 
+/* sw_autotune: chooses the inter-task schedules for this database by
+ * measurement.  For each query-length bucket (m < 256, < 768, < 2048, longer)
+ * it times every candidate (rows, waves) of the single-query kernel on one
+ * random query of a representative length (192, 448, 1280, 4096 residues),
+ * and of the batched kernel on one pair of such queries, with HIP events
+ * around the kernels, and keeps the candidate with the highest GCUPS.
+ * Later searches on the handle (and contexts created afterwards) use the
+ * tuned entry of their query's bucket unless SW_OPT_ROWS / SW_OPT_WAVES are
+ * set.  Takes about a second on a 200,000-sequence database.  `report` may
+ * be NULL.  Errors leave the handle untuned. */
+#define SW_TUNE_BUCKETS 4
+#define SW_TUNE_CANDIDATES 4
+typedef struct sw_tune_report {
+  int32_t query_len[SW_TUNE_BUCKETS];            /* representative lengths */
+  int32_t cand_rows[SW_TUNE_CANDIDATES];         /* candidate schedules */
+  int32_t cand_waves[SW_TUNE_CANDIDATES];
+  float gcups[SW_TUNE_BUCKETS][SW_TUNE_CANDIDATES];        /* single-query kernel */
+  float batch_gcups[SW_TUNE_BUCKETS][SW_TUNE_CANDIDATES];  /* batched kernel */
+  int32_t rows[SW_TUNE_BUCKETS], waves[SW_TUNE_BUCKETS];   /* chosen */
+  int32_t batch_rows[SW_TUNE_BUCKETS], batch_waves[SW_TUNE_BUCKETS];
+} sw_tune_report;
+int sw_autotune(sw_db* db, sw_tune_report* report);
+
 /* ----------------------------------------------------------- search contexts
  * A database handle carries one search context; sw_ctx_create adds more, each
  * with private scratch (boundary rows, profiles, rescoring list, batch plan),

@@ -124,6 +124,23 @@ class Database:
         _native.check(_native.lib().sw_get_stats(self._h, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in _native.Stats._fields_}
 
+    def autotune(self) -> dict:
+        """Measures the candidate schedules on this database (sw_autotune) and
+        returns the report; later searches use the chosen ones."""
+        rep = _native.TuneReport()
+        _native.check(_native.lib().sw_autotune(self._h, ctypes.byref(rep)))
+        nb, nc = _native.TUNE_BUCKETS, _native.TUNE_CANDIDATES
+        cands = [(rep.cand_rows[c], rep.cand_waves[c]) for c in range(nc)]
+        out = []
+        for b in range(nb):
+            out.append({"query_len": rep.query_len[b],
+                        "gcups": {"%dx%d" % cands[c]: rep.gcups[b][c] for c in range(nc)},
+                        "batch_gcups": {"%dx%d" % cands[c]: rep.batch_gcups[b][c]
+                                        for c in range(nc)},
+                        "chosen": (rep.rows[b], rep.waves[b]),
+                        "batch_chosen": (rep.batch_rows[b], rep.batch_waves[b])})
+        return {"buckets": out}
+
     def search(self, query, matrix, gap_open: int = 10, gap_extend: int = 2) -> np.ndarray:
         """Scores of one query against every sequence (host in, host out)."""
         q = _u8(query)

@@ -49,6 +49,20 @@ class Stats(ctypes.Structure):
                 ("rows", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+TUNE_BUCKETS, TUNE_CANDIDATES = 4, 4
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("query_len", ctypes.c_int32 * TUNE_BUCKETS),
+                ("cand_rows", ctypes.c_int32 * TUNE_CANDIDATES),
+                ("cand_waves", ctypes.c_int32 * TUNE_CANDIDATES),
+                ("gcups", (ctypes.c_float * TUNE_CANDIDATES) * TUNE_BUCKETS),
+                ("batch_gcups", (ctypes.c_float * TUNE_CANDIDATES) * TUNE_BUCKETS),
+                ("rows", ctypes.c_int32 * TUNE_BUCKETS), ("waves", ctypes.c_int32 * TUNE_BUCKETS),
+                ("batch_rows", ctypes.c_int32 * TUNE_BUCKETS),
+                ("batch_waves", ctypes.c_int32 * TUNE_BUCKETS)]
+
+
 # name -> (restype, argtypes); every symbol include/swdb.h declares
 P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
 SIGNATURES = {
@@ -63,6 +77,7 @@ SIGNATURES = {
     "sw_last_error": (ctypes.c_char_p, []),
     "sw_set_option": (ctypes.c_int, [P, I32, I64]),
     "sw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
+    "sw_autotune": (ctypes.c_int, [P, ctypes.POINTER(TuneReport)]),
     "sw_plan": (ctypes.c_int, [P, P, I64, I32, ctypes.POINTER(PlanInfo)]),
     "sw_ctx_create": (ctypes.c_int, [P, ctypes.POINTER(P)]),
     "sw_ctx_free": (None, [P]),

@@ -179,6 +179,9 @@ struct Searcher {
   bool use_graphs = true;
   int32_t sat_limit = 32767;
   int32_t opt_rows = 0, opt_waves = 0, opt_intra_rows = 0, opt_intra_waves = 0;
+  // autotuned (rows, waves) per query-length bucket; 0 = not tuned
+  int32_t tune_rows[SW_TUNE_BUCKETS] = {}, tune_waves[SW_TUNE_BUCKETS] = {};
+  int32_t tune_brows[SW_TUNE_BUCKETS] = {}, tune_bwaves[SW_TUNE_BUCKETS] = {};
   sw_stats stats{};                 // since the last sw_get_stats
   std::mutex mtx;
 };
@@ -276,14 +279,23 @@ int validate_search(const Searcher* db, const void* query, int32_t m, const int8
   return SW_OK;
 }
 
+int tune_bucket(int m) {
+  static const int upper[SW_TUNE_BUCKETS - 1] = {256, 768, 2048};
+  int b = 0;
+  while (b < SW_TUNE_BUCKETS - 1 && m >= upper[b]) ++b;
+  return b;
+}
+
 int pick_rows(const Searcher* db, int m) {
   if (db->opt_rows) return db->opt_rows;
+  if (db->tune_rows[tune_bucket(m)]) return db->tune_rows[tune_bucket(m)];
   const int pad32 = (m + 31) / 32 * 32, pad16 = (m + 15) / 16 * 16;
   return (pad32 - m) * 16 <= (pad16 - m) * 16 + m / 8 ? 32 : 16;  // R=32 unless it pads much more
 }
 
-int pick_waves(const Searcher* db, int n_strips) {
+int pick_waves(const Searcher* db, int n_strips, int m) {
   if (db->opt_waves) return db->opt_waves;
+  if (db->tune_waves[tune_bucket(m)]) return db->tune_waves[tune_bucket(m)];
   // more waves per bin shortens each bin's strip pipeline; measured best at 8
   // even when some waves idle in the last round
   (void)n_strips;
@@ -367,7 +379,7 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   const int R = pick_rows(db, m);
   const int m_pad = (m + R - 1) / R * R;
   const int n_strips = m_pad / R;
-  const int W = pick_waves(db, n_strips);
+  const int W = pick_waves(db, n_strips, m);
   int RR = 8, W2 = 1, RRr = 8, W2r = 1;
   pick_intra(db, m, 8, &RR, &W2);     // long sequences
   pick_intra(db, m, 2, &RRr, &W2r);   // rescoring (usually empty)
@@ -476,8 +488,21 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
 int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int32_t nq,
                   const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out) {
   BatchPlan& B = db->batch;
-  const int R = db->opt_rows ? db->opt_rows : 32;
-  const int W = (db->opt_waves == 4 || db->opt_waves == 8) ? db->opt_waves : 8;
+  // schedule: options, else the autotuned entry of the median query length,
+  // else 32 rows x 8 waves
+  int R = 32, W = 8;
+  {
+    std::vector<int64_t> lens;
+    for (int32_t q = 0; q < nq; ++q)
+      if (qoffs[q + 1] > qoffs[q]) lens.push_back(qoffs[q + 1] - qoffs[q]);
+    if (!lens.empty()) {
+      std::nth_element(lens.begin(), lens.begin() + lens.size() / 2, lens.end());
+      const int b = tune_bucket((int)lens[lens.size() / 2]);
+      if (db->tune_brows[b]) { R = db->tune_brows[b]; W = db->tune_bwaves[b]; }
+    }
+  }
+  if (db->opt_rows) R = db->opt_rows;
+  if (db->opt_waves == 4 || db->opt_waves == 8) W = db->opt_waves;
   std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
   if (B.valid && B.qoffs == qv && memcmp(&B.mat, &mat, sizeof(mat)) == 0 && B.go == go &&
       B.ge == ge && B.d_queries == d_queries && B.d_out == d_out && B.R == R && B.W == W &&
@@ -1043,6 +1068,124 @@ static int impl_get_stats(swdb::Searcher* db, sw_stats* out) {
   return SW_OK;
 }
 
+// ---------------------------------------------------------------- autotuner
+// Times each candidate schedule of the single-query and batched inter-task
+// kernels on this database with one random query (or query pair) of a
+// representative length per bucket, and keeps the fastest per bucket.
+static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
+  using namespace swdb;
+  if (!db) return fail(SW_EINVAL, "db is NULL");
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) return SW_OK;
+  static const int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
+  static const int cand_r[SW_TUNE_CANDIDATES] = {16, 16, 32, 32};
+  static const int cand_w[SW_TUNE_CANDIDATES] = {4, 8, 4, 8};
+  hipError_t e;
+  hipStream_t s = db->own_stream;
+  Matrix mat{};
+  // a BLOSUM-like synthetic matrix is enough to time the kernels: the cost
+  // does not depend on the scores; +5 on the diagonal, -1 elsewhere
+  for (int a = 0; a < SW_ALPHA; ++a)
+    for (int b = 0; b < SW_ALPHA; ++b) mat.v[a * SW_ALPHA + b] = (int8_t)(a == b ? 5 : -1);
+  const int max_m = rep_len[SW_TUNE_BUCKETS - 1];
+  DevBuf<uint8_t> dq;
+  DevBuf<int32_t> dout;
+  dq.users = &db->users;
+  dout.users = &db->users;
+  struct Release {
+    DevBuf<uint8_t>& a;
+    DevBuf<int32_t>& b;
+    ~Release() { a.release(); b.release(); }
+  } release_guard{dq, dout};
+  if ((e = dq.reserve((size_t)2 * max_m)) != hipSuccess ||
+      (e = dout.reserve((size_t)2 * db->d->n_seqs)) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("autotune buffers: ") + hipGetErrorString(e));
+  std::vector<uint8_t> hq((size_t)2 * max_m);
+  uint32_t x = 12345u;
+  for (auto& c : hq) { x = x * 1103515245u + 12345u; c = (uint8_t)((x >> 16) % 20); }
+  if ((e = hipMemcpy(dq.p, hq.data(), hq.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "autotune upload");
+  const bool saved_timing = db->timing, saved_graphs = db->use_graphs;
+  const int32_t saved_r = db->opt_rows, saved_w = db->opt_waves;
+  db->timing = true;
+  db->use_graphs = false;
+  sw_tune_report local{};
+  int rc = SW_OK;
+  for (int b = 0; b < SW_TUNE_BUCKETS && rc == SW_OK; ++b) {
+    const int m = rep_len[b];
+    local.query_len[b] = m;
+    double best = -1, bbest = -1;
+    for (int c = 0; c < SW_TUNE_CANDIDATES && rc == SW_OK; ++c) {
+      db->opt_rows = cand_r[c];
+      db->opt_waves = cand_w[c];
+      // single query: warm up, then two timed launches
+      for (int rpt = 0; rpt < 3 && rc == SW_OK; ++rpt) {
+        if (rpt == 1) { db->timed.clear(); db->stats = sw_stats{}; }
+        rc = enqueue_search(db, dq.p, m, mat, 10, 2, dout.p, s);
+      }
+      if (rc != SW_OK) break;
+      float ms_inter = 0;
+      for (auto& t : db->timed) {
+        (void)hipEventSynchronize(t.b);
+        float ms = 0;
+        if (t.kind == kTimeInter && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) ms_inter += ms;
+        db->ev_pool.push_back(t.a);
+        db->ev_pool.push_back(t.b);
+      }
+      db->timed.clear();
+      const double gc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
+      local.gcups[b][c] = (float)gc;
+      if (gc > best) { best = gc; db->tune_rows[b] = cand_r[c]; db->tune_waves[b] = cand_w[c]; }
+      // batched: one pair of queries of this length
+      const int64_t qo[3] = {0, m, 2 * (int64_t)m};
+      db->stats = sw_stats{};
+      for (int rpt = 0; rpt < 2 && rc == SW_OK; ++rpt) {
+        if (rpt == 1) { db->timed.clear(); db->stats = sw_stats{}; }
+        rc = run_batch(db, dq.p, qo, 2, mat, 10, 2, dout.p, s);
+      }
+      if (rc != SW_OK) break;
+      ms_inter = 0;
+      for (auto& t : db->timed) {
+        (void)hipEventSynchronize(t.b);
+        float ms = 0;
+        if (t.kind == kTimeInter && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) ms_inter += ms;
+        db->ev_pool.push_back(t.a);
+        db->ev_pool.push_back(t.b);
+      }
+      db->timed.clear();
+      const double bgc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
+      local.batch_gcups[b][c] = (float)bgc;
+      if (bgc > bbest) { bbest = bgc; db->tune_brows[b] = cand_r[c]; db->tune_bwaves[b] = cand_w[c]; }
+    }
+    local.rows[b] = db->tune_rows[b];
+    local.waves[b] = db->tune_waves[b];
+    local.batch_rows[b] = db->tune_brows[b];
+    local.batch_waves[b] = db->tune_bwaves[b];
+  }
+  (void)hipStreamSynchronize(s);
+  db->batch.release();
+  db->timing = saved_timing;
+  db->use_graphs = saved_graphs;
+  db->opt_rows = saved_r;
+  db->opt_waves = saved_w;
+  db->stats = sw_stats{};
+  for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
+    for (int c = 0; c < SW_TUNE_CANDIDATES; ++c) {
+      local.cand_rows[c] = cand_r[c];
+      local.cand_waves[c] = cand_w[c];
+    }
+  if (rc != SW_OK) {
+    for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
+      db->tune_rows[b] = db->tune_waves[b] = db->tune_brows[b] = db->tune_bwaves[b] = 0;
+    return rc;
+  }
+  if (rep) *rep = local;
+  set_error("");
+  return SW_OK;
+}
+
 // ------------------------------------------------------------ public entry
 // points: a database handle searches with its own searcher, a context with
 // its private one.
@@ -1074,6 +1217,7 @@ int sw_set_option(sw_db* h, int32_t key, int64_t value) {
   return impl_set_option(S_of(h), key, value);
 }
 int sw_get_stats(sw_db* h, sw_stats* out) { return impl_get_stats(S_of(h), out); }
+int sw_autotune(sw_db* h, sw_tune_report* report) { return impl_autotune(S_of(h), report); }
 
 int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
   using namespace swdb;
@@ -1101,6 +1245,12 @@ int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
     c->s.opt_waves = h->main.opt_waves;
     c->s.opt_intra_rows = h->main.opt_intra_rows;
     c->s.opt_intra_waves = h->main.opt_intra_waves;
+    for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
+      c->s.tune_rows[b] = h->main.tune_rows[b];
+      c->s.tune_waves[b] = h->main.tune_waves[b];
+      c->s.tune_brows[b] = h->main.tune_brows[b];
+      c->s.tune_bwaves[b] = h->main.tune_bwaves[b];
+    }
   }
   *out_ctx = c;
   set_error("");

@@ -345,3 +345,23 @@ def test_batch_workload_scaled(sw):
     for qi in range(0, len(w.queries), 7):
         want = ocpu.search(w.queries[qi], w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
         assert (got[qi][ids] == want).all(), qi
+
+
+def test_autotune_then_searches_stay_exact(sw):
+    res, offs = _ragged_db(30)
+    qs = _queries(31, [150, 700, 1300, 2500])
+    say("autotune")
+    with sw.Database(res, offs) as db:
+        rep = db.autotune()
+        assert len(rep["buckets"]) == 4
+        for b in rep["buckets"]:
+            assert b["chosen"] in [(16, 4), (16, 8), (32, 4), (32, 8)]
+            assert b["batch_chosen"] in [(16, 4), (16, 8), (32, 4), (32, 8)]
+            assert max(b["gcups"].values()) > 0 and max(b["batch_gcups"].values()) > 0
+        single = [db.search(q, B62, 10, 2) for q in qs]
+        batch = db.search_batch(qs, B62, 10, 2)
+        ctx = db.context()           # contexts inherit the tuned table
+        ctx.close()
+    for q, a, b in zip(qs, single, batch):
+        want = _oracle(q, res, offs)
+        assert (a == want).all() and (b == want).all()
