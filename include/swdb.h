@@ -151,7 +151,8 @@ enum sw_option {
   SW_OPT_SAT_LIMIT = 2,   /* 0..32767: 16-bit scores >= limit are rescored in
                              32 bits (default 32767; 0 rescores everything) */
   SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto), 16, 32 */
-  SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8 */
+  SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12
+                             (12 only with 16 rows) */
   SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
   SW_OPT_INTRA_WAVES = 6, /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
   SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph
@@ -244,7 +245,7 @@ int sw_ctx_get_stats(sw_ctx* ctx, sw_stats* out);
  */
 #define SW_BIN_SEQS 128
 #define SW_PAD_CODE 24
-#define SW_MIN_BIN_LEN 64
+#define SW_MIN_BIN_LEN 96
 
 typedef struct sw_plan_info {
   int64_t n_bins;          /* bins of short sequences */

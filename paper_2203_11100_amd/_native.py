@@ -17,7 +17,7 @@ SW_OK, SW_EINVAL, SW_ERANGE, SW_ENOMEM, SW_EDEVICE, SW_EBUSY = range(6)
 SW_ALPHA = 24
 SW_BIN_SEQS = 128
 SW_PAD_CODE = 24
-SW_MIN_BIN_LEN = 64
+SW_MIN_BIN_LEN = 96
 SW_DEFAULT_LONG_THRESHOLD = 2048
 SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 1, 2, 3, 4, 5
 SW_OPT_INTRA_WAVES = 6

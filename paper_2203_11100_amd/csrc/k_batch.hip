@@ -179,7 +179,7 @@ hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t 
   if (grid <= 0) return hipSuccess;
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return launch_rw<r, w>(grid, a, s);
-  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }
@@ -187,7 +187,7 @@ hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t 
 int batch_workgroups_per_cu(int R, int W) {
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return occupancy<r, w>();
-  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+  SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
 #undef SWDB_CASE
   return 1;
 }

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
         if (c + 1 < C2) fetch(p, c + 1);
         else if (more) fetch(p + W2, 0);
         int collh = 0, collf = 0;
+#pragma unroll 2
         for (int tau = 0; tau < 64; ++tau) {
           code = shr_in(code, fcode);
           const int hup = shr_in(hbot, fh);

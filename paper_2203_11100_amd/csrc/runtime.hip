@@ -286,20 +286,22 @@ int tune_bucket(int m) {
   return b;
 }
 
+// Default schedule of the inter-task kernels: 16-row strips and 12 waves per
+// bin (three waves per SIMD at 136 VGPRs; measured faster than 32 x 8 for
+// every query length of the plain workload and for the batched one).
+constexpr int kDefaultRows = 16, kDefaultWaves = 12;
+
 int pick_rows(const Searcher* db, int m) {
   if (db->opt_rows) return db->opt_rows;
   if (db->tune_rows[tune_bucket(m)]) return db->tune_rows[tune_bucket(m)];
-  const int pad32 = (m + 31) / 32 * 32, pad16 = (m + 15) / 16 * 16;
-  return (pad32 - m) * 16 <= (pad16 - m) * 16 + m / 8 ? 32 : 16;  // R=32 unless it pads much more
+  return kDefaultRows;
 }
 
 int pick_waves(const Searcher* db, int n_strips, int m) {
+  (void)n_strips;
   if (db->opt_waves) return db->opt_waves;
   if (db->tune_waves[tune_bucket(m)]) return db->tune_waves[tune_bucket(m)];
-  // more waves per bin shortens each bin's strip pipeline; measured best at 8
-  // even when some waves idle in the last round
-  (void)n_strips;
-  return 8;
+  return kDefaultWaves;
 }
 
 // Rows per lane (R) and waves (W2) of the intra-task kernel for a query of
@@ -379,7 +381,8 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   const int R = pick_rows(db, m);
   const int m_pad = (m + R - 1) / R * R;
   const int n_strips = m_pad / R;
-  const int W = pick_waves(db, n_strips, m);
+  int W = pick_waves(db, n_strips, m);
+  if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
   int RR = 8, W2 = 1, RRr = 8, W2r = 1;
   pick_intra(db, m, 8, &RR, &W2);     // long sequences
   pick_intra(db, m, 2, &RRr, &W2r);   // rescoring (usually empty)
@@ -489,8 +492,8 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
                   const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out) {
   BatchPlan& B = db->batch;
   // schedule: options, else the autotuned entry of the median query length,
-  // else 32 rows x 8 waves
-  int R = 32, W = 8;
+  // else the default
+  int R = kDefaultRows, W = kDefaultWaves;
   {
     std::vector<int64_t> lens;
     for (int32_t q = 0; q < nq; ++q)
@@ -502,7 +505,8 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
     }
   }
   if (db->opt_rows) R = db->opt_rows;
-  if (db->opt_waves == 4 || db->opt_waves == 8) W = db->opt_waves;
+  if (db->opt_waves == 4 || db->opt_waves == 8 || db->opt_waves == 12) W = db->opt_waves;
+  if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
   std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
   if (B.valid && B.qoffs == qv && memcmp(&B.mat, &mat, sizeof(mat)) == 0 && B.go == go &&
       B.ge == ge && B.d_queries == d_queries && B.d_out == d_out && B.R == R && B.W == W &&
@@ -1007,8 +1011,8 @@ static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
       db->opt_rows = (int32_t)value;
       return SW_OK;
     case SW_OPT_WAVES:
-      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
-        return fail(SW_EINVAL, "waves must be 0, 1, 2, 4 or 8");
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 12)
+        return fail(SW_EINVAL, "waves must be 0, 1, 2, 4, 8 or 12");
       db->opt_waves = (int32_t)value;
       return SW_OK;
     case SW_OPT_INTRA_ROWS:
@@ -1081,7 +1085,7 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
   if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) return SW_OK;
   static const int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
   static const int cand_r[SW_TUNE_CANDIDATES] = {16, 16, 32, 32};
-  static const int cand_w[SW_TUNE_CANDIDATES] = {4, 8, 4, 8};
+  static const int cand_w[SW_TUNE_CANDIDATES] = {8, 12, 4, 8};
   hipError_t e;
   hipStream_t s = db->own_stream;
   Matrix mat{};

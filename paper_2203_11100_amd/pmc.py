@@ -1,0 +1,59 @@
+"""Workload driver for hardware-counter runs (rocprofv3 --pmc).
+
+Runs, in one process:
+  1. a plain device-to-device copy of COPY_MIB MiB (torch), the calibration
+     kernel of known traffic: COPY_MIB MiB read and COPY_MIB MiB written;
+  2. the plain benchmark workload's searches for the chosen queries (default:
+     all 20), with the database already resident.
+
+Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
+block per run) each dispatch gets its counter value; dividing a search
+kernel's value by the copy kernel's value per MiB converts it into bytes.
+
+    python -m paper_2203_11100_amd.pmc [--queries 0,19] [--copy-mib 1024]
+"""
+import argparse
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+COPY_MIB = 1024
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--queries", default="all")
+    ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
+    args = ap.parse_args()
+    import numpy as np
+    import torch
+    import paper_2203_11100_amd as sw
+    import swinputs
+
+    n = args.copy_mib << 20
+    a = torch.ones(n // 4, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    w = swinputs.config("plain")
+    idx = range(len(w.queries)) if args.queries == "all" else [int(x) for x in args.queries.split(",")]
+    with sw.Database(w.residues, w.offsets) as db:
+        out = torch.empty(db.n_seqs, dtype=torch.int32, device="cuda")
+        info = []
+        for i in idx:
+            q = torch.from_numpy(w.queries[i]).cuda()
+            db.search_async(q, w.matrix, w.gap_open, w.gap_extend, out)
+            torch.cuda.synchronize()
+            st = db.stats()
+            info.append({"query": i, "m": len(w.queries[i]), "inter_cells": st["inter_cells"],
+                         "rows": st["rows"], "waves": st["waves"]})
+    print(json.dumps({"copy_mib": args.copy_mib, "searches": info}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

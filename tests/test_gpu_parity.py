@@ -62,8 +62,8 @@ def test_ragged_database_query_lengths(sw, m):
     assert (got == _oracle(q, res, offs)).all()
 
 
-@pytest.mark.parametrize("rows", [16, 32])
-@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("rows,waves", [(16, 1), (16, 2), (16, 4), (16, 8), (16, 12),
+                                        (32, 1), (32, 2), (32, 4), (32, 8)])
 def test_strip_and_wave_options(sw, rows, waves):
     res, offs = _ragged_db(1)
     q = swinputs.random_residues(333, np.random.default_rng(5))
@@ -279,7 +279,7 @@ def test_batch_matches_oracle(sw, graphs):
         assert (row == _oracle(q, res, offs)).all()
 
 
-@pytest.mark.parametrize("rows,waves", [(16, 4), (16, 8), (32, 4), (32, 8)])
+@pytest.mark.parametrize("rows,waves", [(16, 4), (16, 8), (16, 12), (32, 4), (32, 8)])
 def test_batch_strip_options(sw, rows, waves):
     res, offs = _ragged_db(22)
     qs = _queries(23, [300, 280, 90, 31])
@@ -355,8 +355,8 @@ def test_autotune_then_searches_stay_exact(sw):
         rep = db.autotune()
         assert len(rep["buckets"]) == 4
         for b in rep["buckets"]:
-            assert b["chosen"] in [(16, 4), (16, 8), (32, 4), (32, 8)]
-            assert b["batch_chosen"] in [(16, 4), (16, 8), (32, 4), (32, 8)]
+            assert b["chosen"] in [(16, 8), (16, 12), (32, 4), (32, 8)]
+            assert b["batch_chosen"] in [(16, 8), (16, 12), (32, 4), (32, 8)]
             assert max(b["gcups"].values()) > 0 and max(b["batch_gcups"].values()) > 0
         single = [db.search(q, B62, 10, 2) for q in qs]
         batch = db.search_batch(qs, B62, 10, 2)
@@ -365,3 +365,27 @@ def test_autotune_then_searches_stay_exact(sw):
     for q, a, b in zip(qs, single, batch):
         want = _oracle(q, res, offs)
         assert (a == want).all() and (b == want).all()
+
+
+def test_full_size_long_mix_workload_sampled(sw):
+    """The long-sequence mix at full size (50,000 sequences, 2% of 10,000 to
+    35,000 residues; 10 queries of 1,000..10,000), single searches and one
+    batch: the planted copies of the 10,000-residue query score their closed
+    form (> 16 bits), and a sample of short and long sequences is checked by
+    the oracle for every query."""
+    w = swinputs.config("long-mix")
+    lens = np.diff(w.offsets)
+    rng = np.random.default_rng(40)
+    long_ids = np.nonzero(lens >= 10_000)[0]
+    ids = np.unique(np.concatenate([rng.choice(np.nonzero(lens < 10_000)[0], 24, replace=False),
+                                    rng.choice(long_ids, 2, replace=False)]))
+    diag = int(sum(int(B62[c, c]) for c in w.queries[-1]))
+    say("long-mix full: %d seqs, %d residues" % (w.n_seqs, w.n_residues))
+    with sw.Database(w.residues, w.offsets) as db:
+        single = np.stack([db.search(q, w.matrix, 10, 2) for q in w.queries])
+        batch = db.search_batch(w.queries, w.matrix, 10, 2)
+    assert (single == batch).all()
+    assert diag > 32767 and (single[-1][w.planted] == diag).all()
+    for qi, q in enumerate(w.queries):
+        want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
+        assert (single[qi][ids] == want).all(), qi
