@@ -29,9 +29,36 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
+# HBM traffic of the inter-task kernel on this workload, from rocprofv3
+# --pmc FETCH_SIZE and WRITE_SIZE passes over one step's 20 launches (the
+# counter summary in profiles/ gives the commands and per-launch values),
+# converted to bytes with the counters' readings for a 1 GiB device copy.
+# Valid only for the kernel sources and schedule it was taken on: bench
+# reports null when their digest or the schedule differs.
+TRAFFIC = {"bytes_per_launch": 1.3158e10, "fetch_bytes": 51.41e9, "write_bytes": 211.76e9,
+           "launches": 20, "rows": 16, "waves": 12,
+           "sources_sha256": "c0bc6499ed417666d6f6810f8d02b10463947a29b01b64a1f0085293db83518a"}
+TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 packed 16-bit ops x 2.4 GHz
 PEAK_INT16_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 OPS_PER_CELL = 10
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_11100_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(rows, waves):
+    """Counter-measured bytes per launch, or None when the kernel changed."""
+    t = TRAFFIC
+    if (rows, waves) != (t["rows"], t["waves"]) or sources_digest() != t["sources_sha256"]:
+        return None
+    return t["bytes_per_launch"]
 
 
 def log(*a):
@@ -122,7 +149,10 @@ def main():
     inter_s = st["ms_inter"] / 1e3
     achieved = st["inter_cells"] * OPS_PER_CELL / inter_s / 1e12 if inter_s > 0 else None
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_INT16_TOPS, "unit": "Tops/s",
-            "frac": (achieved / PEAK_INT16_TOPS) if achieved else None, "traffic": None,
+            "frac": (achieved / PEAK_INT16_TOPS) if achieved else None,
+            "traffic": measured_traffic(st["rows"], st["waves"]),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, mean over the "
+                            "step's 20 launches)",
             "kernel": "k_inter_i16 (rows %d, waves %d)" % (st["rows"], st["waves"]),
             "avg_launch_ms": st["ms_inter"] / n_launch,
             "ops_per_cell": OPS_PER_CELL}
