@@ -17,8 +17,9 @@
  *
  * Scores are exact 32-bit integers, identical to Gotoh's H/E/F recurrence
  * evaluated in unbounded integers.  Internally most cells are computed in
- * saturating 16-bit arithmetic; any sequence whose 16-bit score reaches the
- * saturation limit is rescored exactly in 32-bit arithmetic, and sequences
+ * packed IEEE half precision, which is exact for integers up to 2048; any
+ * sequence whose half-precision score reaches the rescoring limit (at most
+ * 2048) is rescored exactly in 32-bit integer arithmetic, and sequences
  * at least `long_threshold` residues long are scored by a 32-bit intra-task
  * (anti-diagonal wavefront) kernel (paper section 2.3: inter-task or
  * intra-task parallelism depending on the sequence length).
@@ -148,8 +149,10 @@ const char* sw_last_error(void);
  * SW_EINVAL.  */
 enum sw_option {
   SW_OPT_TIMING = 1,      /* 0/1: record HIP events around every kernel */
-  SW_OPT_SAT_LIMIT = 2,   /* 0..32767: 16-bit scores >= limit are rescored in
-                             32 bits (default 32767; 0 rescores everything) */
+  SW_OPT_SAT_LIMIT = 2,   /* 0..32767: a sequence whose half-precision score
+                             reaches min(limit, 2048) is rescored in 32-bit
+                             integers (default 32767, i.e. the whole exact
+                             range; 0 rescores everything) */
   SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto), 16, 32 */
   SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12
                              (12 only with 16 rows) */
@@ -241,7 +244,8 @@ int sw_ctx_get_stats(sw_ctx* ctx, sw_stats* out);
  * score with the inter-task kernel.  A bin stores its residues
  * position-major: dword res_off + (p/4)*128 + k holds positions p..p+3 of slot
  * k (byte p%4 = position p), padded with code SW_PAD_CODE up to the bin
- * length, a multiple of 4 and at least SW_MIN_BIN_LEN.
+ * length, a multiple of 4 and at least SW_MIN_BIN_LEN.  Each byte holds
+ * 4 x the residue code (the code's byte offset in a 32-bit profile row).
  */
 #define SW_BIN_SEQS 128
 #define SW_PAD_CODE 24

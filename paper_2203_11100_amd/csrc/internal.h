@@ -23,8 +23,8 @@ struct Matrix {
 
 // Inter-task profile: for each pair of query rows (2r, 2r+1), 26 dwords
 // (codes 0..23, the pad code 24, one spare); dword (r, c) = score of row 2r
-// against code c in bits 0..15, of row 2r+1 in bits 16..31.  13 dwords per
-// query row.
+// against code c in bits 0..15, of row 2r+1 in bits 16..31, as binary16.
+// 13 dwords per query row.
 constexpr int kProfPairDwords = 26;
 constexpr int kProfRowDwords = 13;
 // Score given to padding (pad code, and query rows past the end).  Any value
@@ -33,19 +33,35 @@ constexpr int kPadScore = -64;
 // Intra-task profile (int8, [code][row]) has the 24 codes plus the pad code.
 constexpr int kIntraCodes = 25;
 
+// The packed inter-task kernels compute in IEEE binary16, which holds every
+// integer of magnitude <= 2048 exactly.
+constexpr int kHalfExact = 2048;
+
+// binary16 bit pattern of an integer n with |n| <= kHalfExact (exact).
+__host__ __device__ constexpr uint16_t half_bits(int n) {
+  const unsigned a = n < 0 ? (unsigned)-n : (unsigned)n;
+  if (a == 0) return 0;
+  const int e = 31 - __builtin_clz(a);
+  const unsigned mant = (e <= 10 ? a << (10 - e) : a >> (e - 10)) & 0x3ffu;
+  return (uint16_t)((n < 0 ? 0x8000u : 0u) | ((unsigned)(e + 15) << 10) | mant);
+}
+static_assert(half_bits(1) == 0x3c00 && half_bits(-64) == 0xd400 && half_bits(2048) == 0x6800 &&
+                  half_bits(11) == 0x4980 && half_bits(0) == 0,
+              "binary16 encodings");
+
 struct InterArgs {
   const uint2* res2;          // interleaved store viewed as (lo, hi) dword pairs
   const BinDesc* bins;
   int32_t bin_begin;          // first bin of this launch
   int32_t n_strips;           // query strips of R rows
   const uint32_t* prof;       // [n_strips * R][13] dwords
-  uint32_t go2, ge2;          // gap penalties replicated in both 16-bit halves
+  uint32_t go2, ge2;          // gap penalties (binary16, capped at 2048) in both halves
   uint4* rb;                  // boundary-row buffers of all bins
   const int32_t* slot_seq;
   int32_t* out;
   int32_t* flag_count;        // rescoring list: count, then {sid, query}
   int2* flag_list;
-  int32_t sat_limit;
+  int32_t sat_limit;          // rescoring limit, at most the exact range (see effective_limit)
 };
 
 // Per-query parameters of the intra-task kernel.
@@ -69,6 +85,26 @@ struct IntraArgs {
   int2* scratch;              // per-workgroup boundary rows
   int64_t scratch_stride;     // int2 elements per workgroup
   int32_t* out;
+};
+
+// Packed intra-task kernel for the long list of a single search: the two
+// binary16 halves of a lane hold two database sequences (a pair) against
+// the query.
+struct IntraPairArgs {
+  const uint8_t* res;         // contiguous residues, original order
+  const int64_t* offs;
+  const int2* items;          // {sequence a, sequence b or -1}, a not shorter
+  int32_t count;
+  const uint32_t* prof3;      // binary16 [25][m_pad2 / 2] row-pair dwords
+  int32_t m_pad2;             // profile rows: a multiple of 64*R
+  int32_t n_pass;             // passes of 64*R rows covering the query
+  uint32_t go2, ge2;          // gap penalties (binary16, capped at 2048) in both halves
+  int32_t sat_limit;
+  int2* scratch;              // per-workgroup boundary rows {H pair, F pair}
+  int64_t scratch_stride;     // int2 elements per workgroup
+  int32_t* out;
+  int32_t* flag_count;        // rescoring list: count, then {sid, query}
+  int2* flag_list;
 };
 
 // Batched inter-task kernel: the two 16-bit halves of a lane hold two

@@ -108,17 +108,14 @@ __global__ __launch_bounds__(64 * W) void k_batch_i16(BatchArgs a) {
             if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
         }
         uint32_t out_h[4], out_f[4];
+        // residue bytes hold 4 x code, the code's byte offset in a row
+        sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                       [&](int jj, uint32_t (&p)[R]) {
+          const uint32_t* pc = reinterpret_cast<const uint32_t*>(
+              reinterpret_cast<const char*>(slot) + ((rr >> (8 * jj)) & 0xffu));
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const uint32_t* pc = slot + ((rr >> (8 * jj)) & 0xffu);
-          uint32_t hd = hdiag;
-          hdiag = up_h[jj];
-          uint32_t F = up_f[jj];
-#pragma unroll
-          for (int k = 0; k < R; ++k) cell(hd, H[k], E[k], F, best, pc[k * kBatchRowDwords], go, ge);
-          out_h[jj] = H[R - 1];
-          out_f[jj] = F;
-        }
+          for (int k = 0; k < R; ++k) p[k] = pc[k * kBatchRowDwords];
+        });
         if (s < S - 1) {
           uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
           p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
@@ -137,16 +134,17 @@ __global__ __launch_bounds__(64 * W) void k_batch_i16(BatchArgs a) {
     lbest[w][lane] = best;
     __syncthreads();
     if (w == 0) {
+      uint32_t top = lbest[0][lane];
 #pragma unroll
-      for (int x = 1; x < W; ++x) best = vmax(best, lbest[x][lane]);
+      for (int x = 1; x < W; ++x) top = hmax2(top, lbest[x][lane]);
       const int sid = a.slot_seq[bin.slot0 + 2 * lane + half];
       if (sid >= 0) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
           const int qi = hh ? pd.qb : pd.qa;
           if (qi < 0) continue;
-          const int score = (int)((best >> (16 * hh)) & 0xffffu);
-          if (score >= a.sat_limit) {
+          const int score = half_score(top, hh, a.sat_limit);
+          if (score < 0) {
             const int idx = atomicAdd(a.flag_count, 1);
             a.flag_list[idx] = make_int2(sid, qi);
           } else {

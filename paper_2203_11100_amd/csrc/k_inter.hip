@@ -1,22 +1,19 @@
 // Inter-task Smith-Waterman/Gotoh kernel: every lane scores two database
 // sequences against the query (paper section 2.2: inter-task parallelism,
 // one independent alignment matrix per processing element, no communication
-// between elements), in packed saturating 16-bit arithmetic.
+// between elements), in packed half-precision arithmetic.
 //
 // Cells follow Gotoh's recurrence over query rows i and database columns j:
 //   E(i,j) = max(E(i,j-1) - e, H(i,j-1) - o)
 //   F(i,j) = max(F(i-1,j) - e, H(i-1,j) - o)
 //   H(i,j) = max(0, H(i-1,j-1) + S(a_i,b_j), E(i,j), F(i,j)),  score = max H.
-// Two equivalent rewrites make it cheap on packed 16-bit lanes:
-//   * E and F are kept as E' = max(E, 0), F' = max(F, 0).  Because H >= 0,
-//     max(E' - e, H - o, 0) = max(E - e, H - o, 0), so E' obeys the same
-//     update with a floor at 0, and H = max(H_diag + S, E', F') needs no
-//     separate 0.  Unsigned saturating subtraction gives the floor for free.
-//   * H_diag + S uses signed saturating addition.  Every other quantity is
-//     bounded by an earlier H, so the first cell whose true H exceeds 32767
-//     is computed as exactly 32767 and the sequence's maximum becomes 32767;
-//     sequences whose 16-bit maximum reaches the saturation limit are handed
-//     to the exact 32-bit kernel.
+// E and F are kept as E' = max(E, 0), F' = max(F, 0): because H >= 0,
+// max(E' - e, H - o, 0) = max(E - e, H - o, 0), so E' obeys the same update
+// with a floor at 0, and H = max(H_diag + S, E', F') needs no separate 0.
+// gfx950's 3-input packed maximum then gives a cell in 7 packed ops plus
+// half of one for the running maximum.  The values are integers held in
+// binary16, exact below the rescoring limit (packed16.h); sequences whose
+// maximum reaches the limit are handed to the exact 32-bit kernel.
 //
 // Work decomposition.  A workgroup owns one bin of 128 length-sorted
 // sequences (lane l holds the sequences of slots 2l and 2l+1 in the low and
@@ -127,13 +124,15 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
           if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
       }
       uint32_t out_h[4], out_f[4];
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        // one 32-bit LDS read per row pair and code gives two rows' scores;
-        // the lo and hi sequences' reads are interleaved into packed pairs
-        const uint32_t* plo = slot + ((rr.x >> (8 * jj)) & 0xffu);
-        const uint32_t* phi = slot + ((rr.y >> (8 * jj)) & 0xffu);
-        uint32_t p[R];
+      // one 32-bit LDS read per row pair and sequence gives two rows'
+      // scores; a byte permute per row packs the lo and hi sequences'.  The
+      // residue bytes hold 4 x code, the code's byte offset in a row pair.
+      sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                     [&](int jj, uint32_t (&p)[R]) {
+        const uint32_t* plo = reinterpret_cast<const uint32_t*>(
+            reinterpret_cast<const char*>(slot) + ((rr.x >> (8 * jj)) & 0xffu));
+        const uint32_t* phi = reinterpret_cast<const uint32_t*>(
+            reinterpret_cast<const char*>(slot) + ((rr.y >> (8 * jj)) & 0xffu));
 #pragma unroll
         for (int k2 = 0; k2 < R / 2; ++k2) {
           const uint32_t A = plo[k2 * kProfPairDwords], B = phi[k2 * kProfPairDwords];
@@ -141,14 +140,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
           p[2 * k2] = __builtin_amdgcn_perm(B, A, 0x05040100u);
           p[2 * k2 + 1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
         }
-        uint32_t hd = hdiag;
-        hdiag = up_h[jj];
-        uint32_t F = up_f[jj];
-#pragma unroll
-        for (int k = 0; k < R; ++k) cell(hd, H[k], E[k], F, best, p[k], go, ge);
-        out_h[jj] = H[R - 1];
-        out_f[jj] = F;
-      }
+      });
       if (s < S - 1) {
         uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
         p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
@@ -167,15 +159,16 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
   lbest[w][lane] = best;
   __syncthreads();
   if (w != 0) return;
+  uint32_t top = lbest[0][lane];
 #pragma unroll
-  for (int x = 1; x < W; ++x) best = vmax(best, lbest[x][lane]);
+  for (int x = 1; x < W; ++x) top = hmax2(top, lbest[x][lane]);
   const int64_t slot0 = bin.slot0 + 2 * lane;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     const int sid = a.slot_seq[slot0 + half];
     if (sid < 0) continue;
-    const int score = (int)((best >> (16 * half)) & 0xffffu);
-    if (score >= a.sat_limit) {
+    const int score = half_score(top, half, a.sat_limit);
+    if (score < 0) {
       const int idx = atomicAdd(a.flag_count, 1);
       a.flag_list[idx] = make_int2(sid, 0);
     } else {

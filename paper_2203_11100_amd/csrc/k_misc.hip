@@ -12,8 +12,8 @@ __device__ __forceinline__ int profile_score(const uint8_t* __restrict__ q, int 
 }
 
 // Builds both query profiles from the query codes and the substitution
-// matrix: the inter-task row-pair layout (see kProfPairDwords) and the
-// intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
+// matrix: the inter-task row-pair layout (see kProfPairDwords, binary16) and
+// the intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
 // S(a_i, c); rows past the query end and the pad/spare codes get kPadScore.
 // Thread 0 also clears the rescoring list's count.
 __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
@@ -27,8 +27,8 @@ __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
   for (; idx < n1 + n2; idx += stride) {
     if (idx < n1) {
       const int r = (int)(idx / kProfPairDwords), c = (int)(idx % kProfPairDwords);
-      const uint32_t lo = (uint16_t)(int16_t)profile_score(q, m, mat, 2 * r, c);
-      const uint32_t hi = (uint16_t)(int16_t)profile_score(q, m, mat, 2 * r + 1, c);
+      const uint32_t lo = half_bits(profile_score(q, m, mat, 2 * r, c));
+      const uint32_t hi = half_bits(profile_score(q, m, mat, 2 * r + 1, c));
       prof[idx] = lo | (hi << 16);
     } else {
       const int64_t j = idx - n1;
@@ -40,7 +40,7 @@ __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
 
 // Pair profiles and intra-task profiles of a batch.  blockIdx.y < n_pairs
 // selects a pair: dword (i, c) of its [n_strips*R rows][26] profile holds
-// (S(a_i, c), S(b_i, c)) with kPadScore past either query's end.  Larger
+// (S(a_i, c), S(b_i, c)) as binary16, kPadScore past either query's end.  Larger
 // blockIdx.y select a query's intra-task [25][m_pad2] int8 profile.
 __global__ void k_batch_profiles(const uint8_t* __restrict__ queries,
                                  const int64_t* __restrict__ qoffs, Matrix mat,
@@ -59,8 +59,8 @@ __global__ void k_batch_profiles(const uint8_t* __restrict__ queries,
     const int mb = pd.qb >= 0 ? (int)(qoffs[pd.qb + 1] - qoffs[pd.qb]) : 0;
     for (int64_t idx = start; idx < total; idx += stride) {
       const int i = (int)(idx / kBatchRowDwords), c = (int)(idx % kBatchRowDwords);
-      const uint32_t lo = (uint16_t)(int16_t)profile_score(qa, ma, mat, i, c);
-      const uint32_t hi = (uint16_t)(int16_t)profile_score(qb, mb, mat, i, c);
+      const uint32_t lo = half_bits(profile_score(qa, ma, mat, i, c));
+      const uint32_t hi = half_bits(profile_score(qb, mb, mat, i, c));
       prof[pd.prof_off + idx] = lo | (hi << 16);
     }
   } else {

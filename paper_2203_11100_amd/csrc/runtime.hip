@@ -370,6 +370,19 @@ hipError_t reserve_long_scratch(Searcher* db, int grid) {
 }
 
 // Enqueues one query's search on stream s.  All arguments validated.
+// Gap penalty for the half-precision kernels, in both halves: penalties
+// above the exact range act like 2048 there (packed16.h).
+uint32_t half_pair(int32_t g) {
+  const uint32_t h = half_bits(std::min<int32_t>(g, kHalfExact));
+  return h | (h << 16);
+}
+
+// Rescoring limit of the half-precision kernels: the requested limit, at
+// most 2048, below which every value is computed exactly (packed16.h).
+int32_t effective_limit(int32_t requested) {
+  return std::max<int32_t>(0, std::min<int32_t>(requested, kHalfExact));
+}
+
 int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
                    int32_t ge, int32_t* d_out, hipStream_t s) {
   hipError_t e;
@@ -443,23 +456,21 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   a.bin_begin = 0;
   a.n_strips = n_strips;
   a.prof = db->prof.p;
-  const uint32_t go16 = (uint32_t)std::min<int32_t>(go, 65535);
-  const uint32_t ge16 = (uint32_t)std::min<int32_t>(ge, 65535);
-  a.go2 = go16 | (go16 << 16);
-  a.ge2 = ge16 | (ge16 << 16);
+  a.go2 = half_pair(go);
+  a.ge2 = half_pair(ge);
   a.rb = db->rb.p;
   a.slot_seq = db->d->slot_seq.p;
   a.out = d_out;
   a.flag_count = db->flags.p;
   a.flag_list = flag_list(db);
-  a.sat_limit = db->sat_limit;
+  a.sat_limit = effective_limit(db->sat_limit);
   const int n_bins = (int)db->d->plan.n_bins;
   if (n_bins > 0) {
     const int ti = time_begin(db, kTimeInter, s);
     if ((e = launch_inter(R, W, n_bins, a, s)) != hipSuccess) return hip_fail(e, "inter-task kernel");
     time_end(db, ti, s);
     ++db->stats.n_inter_launches;
-    // exact rescoring of sequences whose 16-bit score saturated
+    // exact rescoring of sequences whose half-precision score reached the limit
     IntraArgs ra = ia;
     ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;
@@ -682,10 +693,8 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
     ba.counter = db->counter.p;
     ba.pairs = B.pairs.p;
     ba.prof = B.prof.p;
-    const uint32_t go16 = (uint32_t)std::min<int32_t>(B.go, 65535);
-    const uint32_t ge16 = (uint32_t)std::min<int32_t>(B.ge, 65535);
-    ba.go2 = go16 | (go16 << 16);
-    ba.ge2 = ge16 | (ge16 << 16);
+    ba.go2 = half_pair(B.go);
+    ba.ge2 = half_pair(B.ge);
     ba.rb = db->rb_batch.p;
     ba.rb_stride = (int64_t)(db->d->plan.max_all_bin_len / 4) * 128;
     ba.slot_seq = db->d->slot_seq.p;
@@ -693,7 +702,7 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
     ba.n_seqs = n;
     ba.flag_count = db->flags.p;
     ba.flag_list = flag_list(db);
-    ba.sat_limit = B.sat_limit;
+    ba.sat_limit = effective_limit(B.sat_limit);
     const int ti = time_begin(db, kTimeInter, s);
     if ((e = launch_batch(B.R, B.W, B.grid_b, ba, s)) != hipSuccess)
       return hip_fail(e, "batched inter-task kernel");

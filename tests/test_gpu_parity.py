@@ -110,6 +110,44 @@ def test_forced_rescoring(sw, limit):
         assert st["n_rescored"] == int(in_bins.sum())
     if limit == 40:
         assert st["n_rescored"] == int((want[in_bins] >= 40).sum())
+    if limit == 32767:               # the half-precision kernels' exact range ends at 2048
+        assert st["n_rescored"] == int((want[in_bins] >= 2048).sum())
+
+
+def test_scores_around_the_half_precision_limit(sw):
+    """Planted matches scoring ~1,400..2,500 in the packed kernels' bins:
+    every score exact, and exactly those >= 2048 rescored in 32 bits (single
+    and batched searches)."""
+    rng = np.random.default_rng(31)
+    W = swinputs.ALPHABET.index("W")
+    C = swinputs.ALPHABET.index("C")
+    q = np.concatenate([np.full(100, W, np.uint8), np.full(112, C, np.uint8),
+                        swinputs.random_residues(40, rng)])
+    lengths = rng.integers(50, 600, 400).astype(np.int64)
+    res, offs = swinputs.make_database(lengths, rng)
+    seqs = [res[offs[i]:offs[i + 1]] for i in range(len(lengths))]
+    for k, cut in enumerate((0, 3, 6, 9, 14, 20, 30, 45, 60)):
+        seqs[7 + 31 * k] = np.concatenate([swinputs.random_residues(12, rng), q[cut:],
+                                           swinputs.random_residues(5, rng)])
+    lens = np.array([len(x) for x in seqs], dtype=np.int64)
+    offs = np.zeros(len(lens) + 1, dtype=np.int64)
+    np.cumsum(lens, out=offs[1:])
+    res = np.concatenate(seqs)
+    want = _oracle(q, res, offs)
+    assert ((want >= 1800) & (want < 2048)).any() and (want > 2048).sum() >= 3
+    qs = [q, q[20:].copy(), swinputs.random_residues(90, rng)]
+    say("half-precision limit")
+    with sw.Database(res, offs, long_threshold=10**6) as db:
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+        gotb = db.search_batch(qs, B62, 10, 2)
+        stb = db.stats()
+    assert (got == want).all()
+    assert st["n_rescored"] == int((want >= 2048).sum())
+    wants = [_oracle(x, res, offs) for x in qs]
+    for row, wq in zip(gotb, wants):
+        assert (row == wq).all()
+    assert stb["n_rescored"] == sum(int((wq >= 2048).sum()) for wq in wants)
 
 
 def test_planted_overflow_in_short_bins(sw):
