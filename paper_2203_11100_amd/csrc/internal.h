@@ -139,11 +139,13 @@ struct BatchArgs {
 
 // Kernel launchers (return hipSuccess or the launch error).
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
-                          int m_pad, int8_t* prof2, int m_pad2, int32_t* flag_count,
-                          hipStream_t s);
+                          int m_pad, int8_t* prof2, uint32_t* prof3, int m_pad2,
+                          int32_t* flag_count, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_t s);
 hipError_t launch_intra(int RR, int W2, int grid, const IntraArgs& a, hipStream_t s);
+// R in {2, 4, 8}, W2 in {1, 2, 4, 8}, not (8, 8) (LDS)
+hipError_t launch_intra_pairs(int R, int W2, int grid, const IntraPairArgs& a, hipStream_t s);
 hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t s);
 int batch_workgroups_per_cu(int R, int W);
 // Pair profiles for `n_pairs` pairs and intra-task profiles for `n_queries`

@@ -39,6 +39,7 @@
 // code*64R + R*l, so the 64 reads of a wave cover consecutive bytes of one
 // code row each and never conflict on banks.
 #include "internal.h"
+#include "packed16.h"
 
 namespace swdb {
 namespace {
@@ -214,6 +215,178 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
   }
 }
 
+template <int RP> struct PairVec;
+template <> struct PairVec<1> { typedef uint32_t T; static constexpr int n = 1; };
+template <> struct PairVec<2> { typedef uint2 T; static constexpr int n = 2; };
+template <> struct PairVec<4> { typedef uint4 T; static constexpr int n = 4; };
+__device__ __forceinline__ uint32_t pv_get(const uint32_t& v, int) { return v; }
+__device__ __forceinline__ uint32_t pv_get(const uint2& v, int j) { return j ? v.y : v.x; }
+__device__ __forceinline__ uint32_t pv_get(const uint4& v, int j) {
+  return j == 0 ? v.x : j == 1 ? v.y : j == 2 ? v.z : v.w;
+}
+
+// Packed variant for the long list of a single search.  The two halves of
+// every register hold two database sequences (a, b) of similar length scored
+// against the query in binary16, with the cell arithmetic of the inter-task
+// kernels (packed16.h, exact below the rescoring limit); the wavefront,
+// passes, pass pipeline and boundary rows are those of k_intra_i32, each
+// value now carrying both sequences.  The profile is binary16 row pairs
+// [code][row/2]: a lane reads R/2 dwords (its R rows) for each sequence's
+// residue and one byte permute per row packs the two sequences' scores.  The
+// residue codes travel down the wave pre-multiplied into byte offsets of a
+// code row, a's in the low and b's in the high 16 bits of one register.
+// Sequences whose maximum reaches the limit go to the rescoring list.
+template <int R, int W2>
+__global__ __launch_bounds__(64 * W2) void k_intra_h2(IntraPairArgs a) {
+  constexpr int ROWS = 64 * R;        // query rows per pass
+  constexpr int RP = R / 2;           // row-pair dwords per lane and code
+  constexpr int CODE_DW = ROWS / 2;   // dwords per code row of a pass
+  constexpr uint32_t kCodeBytes = CODE_DW * 4;
+  static_assert(SW_PAD_CODE * kCodeBytes < 65536, "code offsets must fit 16 bits");
+  constexpr uint32_t kPadPair = (SW_PAD_CODE * kCodeBytes) * 0x10001u;
+  typedef typename PairVec<RP>::T PV;
+  __shared__ __align__(16) uint32_t lprof_all[W2][kIntraCodes * CODE_DW];
+  __shared__ uint32_t lbest[W2];
+
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t* lprof = &lprof_all[w][0];
+  const char* lbase = reinterpret_cast<const char*>(lprof) + lane * RP * 4;
+  int2* __restrict__ rb = a.scratch + (size_t)blockIdx.x * a.scratch_stride;
+  const uint32_t go = a.go2, ge = a.ge2;
+  const int P = a.n_pass;
+  const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
+  const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
+
+  for (int it = blockIdx.x; it < a.count; it += gridDim.x) {
+    const int2 item = a.items[it];
+    const int sa = item.x, sb = item.y;
+    const int64_t ba = a.offs[sa];
+    const int na = (int)(a.offs[sa + 1] - ba);
+    const int64_t bb = sb >= 0 ? a.offs[sb] : 0;
+    const int nb = sb >= 0 ? (int)(a.offs[sb + 1] - bb) : 0;
+    const int n = na > nb ? na : nb;
+    const uint8_t* __restrict__ sqa = a.res + ba;
+    const uint8_t* __restrict__ sqb = a.res + bb;
+    const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
+    const int T_total = q_last * C2 + kSkew * w_last + C2;
+
+    uint32_t fcode_n = kPadPair, fh_n = 0, ff_n = 0;
+    auto fetch = [&](int p, int c) {
+      const int jf = c * 64 + lane;
+      const uint32_t ca = jf < na ? (uint32_t)sqa[jf] : (uint32_t)SW_PAD_CODE;
+      const uint32_t cb = jf < nb ? (uint32_t)sqb[jf] : (uint32_t)SW_PAD_CODE;
+      fcode_n = ca * kCodeBytes | (cb * kCodeBytes) << 16;
+      fh_n = 0;
+      ff_n = 0;
+      if (p > 0 && jf < n) {
+        const int2 v = rb[jf];
+        fh_n = (uint32_t)v.x;
+        ff_n = (uint32_t)v.y;
+      }
+    };
+
+    uint32_t best = 0;
+    if (w == 0 && my_rounds > 0) fetch(0, 0);
+    for (int T = 0; T < kSkew * w; ++T) {
+      if (T == kSkew * w - 1 && my_rounds > 0) fetch(w, 0);
+      __syncthreads();
+    }
+    for (int q = 0; q < my_rounds; ++q) {
+      const int p = q * W2 + w;
+      const bool more = q + 1 < my_rounds;
+      const bool last_pass = p == P - 1;
+      {  // stage this pass's profile row pairs (read back only by this wave)
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.prof3);
+        uint4* dst = reinterpret_cast<uint4*>(lprof);
+        constexpr int per_code = CODE_DW / 4;          // uint4 per code row
+        const int src_stride = a.m_pad2 / 8;           // uint4 per code in prof3
+        for (int x = lane; x < kIntraCodes * per_code; x += 64) {
+          const int code = x / per_code, r = x - code * per_code;
+          dst[x] = src[(size_t)code * src_stride + (size_t)p * per_code + r];
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      }
+      uint32_t H[R], E[R];
+#pragma unroll
+      for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
+      uint32_t hdiag = 0, code = kPadPair, hbot = 0, fbot = 0;
+      for (int c = 0; c < C2; ++c) {
+        uint32_t fcode = fcode_n, fh = fh_n, ff = ff_n;
+        if (c + 1 < C2) fetch(p, c + 1);
+        else if (more) fetch(p + W2, 0);
+        uint32_t collh = 0, collf = 0;
+#pragma unroll 2
+        for (int tau = 0; tau < 64; ++tau) {
+          code = (uint32_t)shr_in((int)code, (int)fcode);
+          const uint32_t hup = (uint32_t)shr_in((int)hbot, (int)fh);
+          const uint32_t fup = (uint32_t)shr_in((int)fbot, (int)ff);
+          fcode = (uint32_t)shl_in((int)fcode, (int)kPadPair);
+          fh = (uint32_t)shl_in((int)fh, 0);
+          ff = (uint32_t)shl_in((int)ff, 0);
+          const PV va = *reinterpret_cast<const PV*>(lbase + (code & 0xffffu));
+          const PV vb = *reinterpret_cast<const PV*>(lbase + (code >> 16));
+          uint32_t pr[R];
+#pragma unroll
+          for (int j = 0; j < RP; ++j) {
+            const uint32_t A = pv_get(va, j), B = pv_get(vb, j);
+            pr[2 * j] = __builtin_amdgcn_perm(B, A, 0x05040100u);
+            pr[2 * j + 1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+          }
+          uint32_t hd = hdiag;
+          hdiag = hup;
+          uint32_t F = fup;
+          uint32_t hprev = 0;
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const uint32_t h = cell(hd, H[k], E[k], F, pr[k], go, ge);
+            if (k & 1) best = hmax3(best, hprev, h);
+            else hprev = h;
+          }
+          hbot = H[R - 1];
+          fbot = F;
+          collh = (uint32_t)shl_in((int)collh, (int)hbot);
+          collf = (uint32_t)shl_in((int)collf, (int)fbot);
+        }
+        const int jo = c * 64 + lane - 63;
+        if (!last_pass && jo >= 0 && jo < n) rb[jo] = make_int2((int)collh, (int)collf);
+        __syncthreads();
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+    for (int T = kSkew * w + my_rounds * C2; T < T_total; ++T) __syncthreads();
+
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) best = hmax2(best, (uint32_t)__shfl_xor((int)best, off, 64));
+    if (lane == 0) lbest[w] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t b = lbest[0];
+#pragma unroll
+      for (int x = 1; x < W2; ++x) b = hmax2(b, lbest[x]);
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int sid = half ? sb : sa;
+        if (sid < 0) continue;
+        const int score = half_score(b, half, a.sat_limit);
+        if (score < 0) {
+          const int idx = atomicAdd(a.flag_count, 1);
+          a.flag_list[idx] = make_int2(sid, 0);
+        } else {
+          a.out[sid] = score;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int R, int W2>
+hipError_t launch_pair_rw(int grid, const IntraPairArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_intra_h2<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
+  return hipGetLastError();
+}
+
 template <int R, int W2>
 hipError_t launch_rw(int grid, const IntraArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_intra_i32<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
@@ -230,6 +403,18 @@ hipError_t launch_intra(int R, int W2, int grid, const IntraArgs& a, hipStream_t
   SWDB_CASE(2, 2) SWDB_CASE(4, 2) SWDB_CASE(8, 2)
   SWDB_CASE(2, 4) SWDB_CASE(4, 4) SWDB_CASE(8, 4)
   SWDB_CASE(2, 8) SWDB_CASE(4, 8) SWDB_CASE(8, 8)
+#undef SWDB_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_intra_pairs(int R, int W2, int grid, const IntraPairArgs& a, hipStream_t s) {
+  if (grid <= 0) return hipSuccess;
+#define SWDB_CASE(r, w) \
+  if (R == r && W2 == w) return launch_pair_rw<r, w>(grid, a, s);
+  SWDB_CASE(2, 1) SWDB_CASE(4, 1) SWDB_CASE(8, 1)
+  SWDB_CASE(2, 2) SWDB_CASE(4, 2) SWDB_CASE(8, 2)
+  SWDB_CASE(2, 4) SWDB_CASE(4, 4) SWDB_CASE(8, 4)
+  SWDB_CASE(2, 8) SWDB_CASE(4, 8)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }

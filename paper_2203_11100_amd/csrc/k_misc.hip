@@ -11,29 +11,40 @@ __device__ __forceinline__ int profile_score(const uint8_t* __restrict__ q, int 
   return qc < SW_ALPHA ? (int)mat.v[qc * SW_ALPHA + c] : kPadScore;
 }
 
-// Builds both query profiles from the query codes and the substitution
-// matrix: the inter-task row-pair layout (see kProfPairDwords, binary16) and
-// the intra-task layout [25][m_pad2] int8 (codes 0..23, pad).  Entry (i, c) is
-// S(a_i, c); rows past the query end and the pad/spare codes get kPadScore.
-// Thread 0 also clears the rescoring list's count.
+// Builds the query profiles from the query codes and the substitution
+// matrix: the inter-task row-pair layout (see kProfPairDwords, binary16),
+// the intra-task layout [25][m_pad2] int8 and, when prof3 is given, the
+// packed intra-task layout [25][m_pad2 / 2] of binary16 row pairs (dword
+// (c, r) = S(a_2r, c) low, S(a_2r+1, c) high); codes 0..23 and the pad code.
+// Entry (i, c) is S(a_i, c); rows past the query end and the pad/spare codes
+// get kPadScore.  Thread 0 also clears the rescoring list's count.
 __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
                           uint32_t* __restrict__ prof, int m_pad, int8_t* __restrict__ prof2,
-                          int m_pad2, int32_t* __restrict__ flag_count) {
+                          uint32_t* __restrict__ prof3, int m_pad2,
+                          int32_t* __restrict__ flag_count) {
   const int64_t n1 = (int64_t)(m_pad / 2) * kProfPairDwords;
   const int64_t n2 = (int64_t)kIntraCodes * m_pad2;
+  const int64_t n3 = prof3 ? (int64_t)kIntraCodes * (m_pad2 / 2) : 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx == 0 && flag_count) *flag_count = 0;
-  for (; idx < n1 + n2; idx += stride) {
+  for (; idx < n1 + n2 + n3; idx += stride) {
     if (idx < n1) {
       const int r = (int)(idx / kProfPairDwords), c = (int)(idx % kProfPairDwords);
       const uint32_t lo = half_bits(profile_score(q, m, mat, 2 * r, c));
       const uint32_t hi = half_bits(profile_score(q, m, mat, 2 * r + 1, c));
       prof[idx] = lo | (hi << 16);
-    } else {
+    } else if (idx < n1 + n2) {
       const int64_t j = idx - n1;
       const int c = (int)(j / m_pad2), i = (int)(j % m_pad2);
       prof2[j] = (int8_t)profile_score(q, m, mat, i, c);
+    } else {
+      const int64_t j = idx - n1 - n2;
+      const int half_rows = m_pad2 / 2;
+      const int c = (int)(j / half_rows), r = (int)(j % half_rows);
+      const uint32_t lo = half_bits(profile_score(q, m, mat, 2 * r, c));
+      const uint32_t hi = half_bits(profile_score(q, m, mat, 2 * r + 1, c));
+      prof3[j] = lo | (hi << 16);
     }
   }
 }
@@ -84,13 +95,14 @@ __global__ void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
 }  // namespace
 
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
-                          int m_pad, int8_t* prof2, int m_pad2, int32_t* flag_count,
-                          hipStream_t s) {
-  const int64_t total = (int64_t)(m_pad / 2) * kProfPairDwords + (int64_t)kIntraCodes * m_pad2;
+                          int m_pad, int8_t* prof2, uint32_t* prof3, int m_pad2,
+                          int32_t* flag_count, hipStream_t s) {
+  const int64_t total = (int64_t)(m_pad / 2) * kProfPairDwords + (int64_t)kIntraCodes * m_pad2 +
+                        (prof3 ? (int64_t)kIntraCodes * (m_pad2 / 2) : 0);
   int grid = (int)std::min<int64_t>((total + 255) / 256, 2048);
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(k_profile, dim3(grid), dim3(256), 0, s, d_query, m, mat, prof, m_pad, prof2,
-                     m_pad2, flag_count);
+                     prof3, m_pad2, flag_count);
   return hipGetLastError();
 }
 

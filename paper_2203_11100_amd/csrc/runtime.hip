@@ -148,6 +148,8 @@ struct DbData {
   DevBuf<uint8_t> res;              // contiguous residues (original order)
   DevBuf<int64_t> offs;
   DevBuf<int2> d_long_items;        // {sid, 0} for the long list
+  DevBuf<int2> d_long_pairs;        // {sid a, sid b or -1}: the long list in pairs
+  int64_t n_long_pairs = 0;
 };
 
 // Everything one search mutates: scratch buffers, streams, events, the
@@ -161,6 +163,7 @@ struct Searcher {
   DevBuf<int32_t> flags;            // [0] count, [2..] {sid, query} rescoring list
   DevBuf<uint32_t> prof;            // per-query buffers, grown on demand
   DevBuf<int8_t> prof2;
+  DevBuf<uint32_t> prof3;           // binary16 row pairs of the packed intra-task kernel
   DevBuf<uint8_t> q_stage;
   DevBuf<int32_t> out_stage;
   BatchPlan batch;
@@ -206,7 +209,8 @@ void release_searcher(Searcher* db) {
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
   if (db->aux_stream) (void)hipStreamSynchronize(db->aux_stream);
   db->rb.release(); db->rb_long.release(); db->rb_resc.release(); db->flags.release();
-  db->prof.release(); db->prof2.release(); db->q_stage.release(); db->out_stage.release();
+  db->prof.release(); db->prof2.release(); db->prof3.release(); db->q_stage.release();
+  db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
   for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out}) {
     if (*e) (void)hipEventDestroy(*e);
@@ -228,6 +232,7 @@ void destroy_db(sw_db* h) {
   DbData& d = h->data;
   d.packed.release(); d.bins.release(); d.slot_seq.release(); d.res.release(); d.offs.release();
   d.d_long_items.release();
+  d.d_long_pairs.release();
   delete h;
 }
 
@@ -235,11 +240,18 @@ void destroy_db(sw_db* h) {
 void bind_buffers(Searcher* S) {
   const StreamSet* u = &S->users;
   S->rb.users = S->rb_long.users = S->rb_resc.users = u;
-  S->prof.users = u; S->prof2.users = u; S->q_stage.users = u; S->out_stage.users = u;
+  S->prof.users = u; S->prof2.users = u; S->prof3.users = u; S->q_stage.users = u;
+  S->out_stage.users = u;
   S->rb_batch.users = S->counter.users = S->flags.users = u;
   BatchPlan& B = S->batch;
   B.pairs.users = u; B.qdesc.users = u; B.items.users = u; B.long_items.users = u;
   B.qoffs_d.users = u; B.prof.users = u; B.prof2.users = u;
+}
+
+// Per-workgroup boundary-row length of the rescoring launch: any sequence of
+// a bin or of the long list may be flagged.
+int64_t rescore_stride(const Plan& P) {
+  return std::max<int64_t>({(int64_t)P.max_all_bin_len, (int64_t)P.max_long_len, 1});
 }
 
 // Allocates a searcher's fixed scratch, streams and events for database d.
@@ -249,9 +261,10 @@ int init_searcher(Searcher* S, DbData* d) {
   const Plan& P = d->plan;
   hipError_t e;
   if ((e = S->rb.reserve((size_t)P.boundary_uint4)) != hipSuccess ||
-      (e = S->rb_resc.reserve((size_t)kIntraGridRescore * std::max<int32_t>(P.max_all_bin_len, 1))) !=
+      (e = S->rb_resc.reserve((size_t)kIntraGridRescore * (size_t)rescore_stride(P))) !=
           hipSuccess ||
-      (e = S->flags.reserve((size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS, 1)))) !=
+      (e = S->flags.reserve(
+           (size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)))) !=
           hipSuccess)
     return fail(SW_ENOMEM, std::string("search scratch: ") + hipGetErrorString(e));
   if ((e = hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking)) != hipSuccess ||
@@ -306,9 +319,12 @@ int pick_waves(const Searcher* db, int n_strips, int m) {
 
 // Rows per lane (R) and waves (W2) of the intra-task kernel for a query of
 // length m: the smallest estimated latency for one long sequence, where a
-// pass of 64R rows costs about (10R + 10) VALU ops per step, waves beyond one
-// per SIMD share it, and the passes run in rounds of W2.
-void pick_intra(const Searcher* db, int m, int max_waves, int* R_out, int* W2_out) {
+// pass of 64R rows costs about (10R + 10) VALU ops per step in int32 and
+// (8R + 24) in the packed binary16 kernel, waves beyond one per SIMD share
+// it, and the passes run in rounds of W2.  The packed kernel has no (8, 8)
+// (its LDS profile would exceed 160 KB).
+void pick_intra(const Searcher* db, int m, int max_waves, int* R_out, int* W2_out,
+                bool packed = false) {
   double best = 1e300;
   int bR = 8, bW = 1;
   for (int R : {2, 4, 8}) {
@@ -316,12 +332,18 @@ void pick_intra(const Searcher* db, int m, int max_waves, int* R_out, int* W2_ou
     const int passes = (m + 64 * R - 1) / (64 * R);
     for (int W2 : {1, 2, 4, 8}) {
       if (W2 > max_waves) continue;
+      if (packed && R == 8 && W2 == 8) continue;
       if (db->opt_intra_waves && max_waves > 2 && W2 != db->opt_intra_waves) continue;
       const int rounds = (passes + W2 - 1) / W2;
       const double share = W2 > 4 ? W2 / 4.0 : 1.0;
-      const double est = rounds * (10.0 * R + 10.0) * share + 1e-3 * W2;
+      const double step = packed ? 8.0 * R + 24.0 : 10.0 * R + 10.0;
+      const double est = rounds * step * share + 1e-3 * W2;
       if (est < best) { best = est; bR = R; bW = W2; }
     }
+  }
+  if (best == 1e300 && packed) {   // only (8, 8) was allowed by the options
+    bR = 8;
+    bW = 4;
   }
   *R_out = bR;
   *W2_out = bW;
@@ -396,10 +418,11 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   const int n_strips = m_pad / R;
   int W = pick_waves(db, n_strips, m);
   if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
+  const int64_t n_long = db->d->plan.n_long;
   int RR = 8, W2 = 1, RRr = 8, W2r = 1;
-  pick_intra(db, m, 8, &RR, &W2);     // long sequences
-  pick_intra(db, m, 2, &RRr, &W2r);   // rescoring (usually empty)
-  // one intra-task profile serves both launches: pad to the larger pass
+  pick_intra(db, m, 8, &RR, &W2, true);   // long sequences, in pairs (binary16)
+  pick_intra(db, m, 2, &RRr, &W2r);       // exact rescoring (usually empty)
+  // the intra-task profiles of both launches: pad to the larger pass
   const int rows2 = 64 * std::max(RR, RRr);
   const int m_pad2 = (m + rows2 - 1) / rows2 * rows2;
 
@@ -407,14 +430,17 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
   if ((e = db->prof2.reserve((size_t)kIntraCodes * m_pad2)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
+  if (n_long > 0 && (e = db->prof3.reserve((size_t)kIntraCodes * (m_pad2 / 2))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
 
   const int t_total = time_begin(db, kTimeTotal, s);
-  if ((e = launch_profile(d_query, m, mat, db->prof.p, m_pad, db->prof2.p, m_pad2, db->flags.p,
-                          s)) != hipSuccess)
+  if ((e = launch_profile(d_query, m, mat, db->prof.p, m_pad, db->prof2.p,
+                          n_long > 0 ? db->prof3.p : nullptr, m_pad2, db->flags.p, s)) !=
+      hipSuccess)
     return hip_fail(e, "profile kernel");
 
-  // long sequences: intra-task kernel on the auxiliary stream, overlapped
-  // with the inter-task bins
+  // long sequences: packed intra-task kernel on the auxiliary stream,
+  // overlapped with the inter-task bins
   IntraArgs ia{};
   ia.res = db->d->res.p;
   ia.offs = db->d->offs.p;
@@ -426,23 +452,31 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   ia.go = go;
   ia.ge = ge;
   ia.out = d_out;
-  const int64_t n_long = db->d->plan.n_long;
   if (n_long > 0) {
     if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
       return hip_fail(e, "stream wait");
-    IntraArgs la = ia;
-    la.items = db->d->d_long_items.p;
-    la.count_ptr = nullptr;
-    la.count = (int32_t)n_long;
-    const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
+    IntraPairArgs la{};
+    la.res = db->d->res.p;
+    la.offs = db->d->offs.p;
+    la.items = db->d->d_long_pairs.p;
+    la.count = (int32_t)db->d->n_long_pairs;
+    la.prof3 = db->prof3.p;
+    la.m_pad2 = m_pad2;
+    la.n_pass = (m + 64 * RR - 1) / (64 * RR);
+    la.go2 = half_pair(go);
+    la.ge2 = half_pair(ge);
+    la.sat_limit = effective_limit(db->sat_limit);
+    const int grid = (int)std::min<int64_t>(db->d->n_long_pairs, kIntraGridLong);
     if ((e = reserve_long_scratch(db, grid)) != hipSuccess)
       return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
     la.scratch = db->rb_long.p;
     la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
-    la.q0.n_pass = (m + 64 * RR - 1) / (64 * RR);
+    la.out = d_out;
+    la.flag_count = db->flags.p;
+    la.flag_list = flag_list(db);
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
-    if ((e = launch_intra(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
+    if ((e = launch_intra_pairs(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
     time_end(db, tl, db->aux_stream);
     if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
@@ -470,21 +504,25 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     if ((e = launch_inter(R, W, n_bins, a, s)) != hipSuccess) return hip_fail(e, "inter-task kernel");
     time_end(db, ti, s);
     ++db->stats.n_inter_launches;
-    // exact rescoring of sequences whose half-precision score reached the limit
+  }
+  // both packed kernels fill the rescoring list: join before consuming it
+  if (n_long > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
+    return hip_fail(e, "stream wait");
+  {
+    // exact rescoring of sequences whose half-precision score reached the
+    // limit; the workgroups read the list's length on the device
     IntraArgs ra = ia;
     ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;
     ra.count = 0;
     ra.scratch = db->rb_resc.p;
-    ra.scratch_stride = std::max<int64_t>(db->d->plan.max_bin_len, 1);
+    ra.scratch_stride = rescore_stride(db->d->plan);
     ra.q0.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
     const int tr = time_begin(db, kTimeRescore, s);
     if ((e = launch_intra(RRr, W2r, kIntraGridRescore, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
     time_end(db, tr, s);
   }
-  if (n_long > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
-    return hip_fail(e, "stream wait");
   time_end(db, t_total, s);
 
   db->stats.rows = R;
@@ -711,7 +749,7 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
     ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;
     ra.scratch = db->rb_resc.p;
-    ra.scratch_stride = std::max<int64_t>(db->d->plan.max_all_bin_len, 1);
+    ra.scratch_stride = rescore_stride(db->d->plan);
     const int tr = time_begin(db, kTimeRescore, s);
     if ((e = launch_intra(B.RR, B.W2r, kIntraGridRescore, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
@@ -820,6 +858,12 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   fill_layout(residues, offsets, P, h_packed.data(), h_bins.data(), h_slots.data(), h_long.data());
   std::vector<int2> h_long_items(h_long.size());
   for (size_t t = 0; t < h_long.size(); ++t) h_long_items[t] = make_int2(h_long[t], 0);
+  // the packed intra-task kernel takes the long list (longest first) in
+  // pairs of neighbours, so the two sequences of a pair have similar lengths
+  std::vector<int2> h_long_pairs((h_long.size() + 1) / 2);
+  for (size_t t = 0; t < h_long_pairs.size(); ++t)
+    h_long_pairs[t] = make_int2(h_long[2 * t], 2 * t + 1 < h_long.size() ? h_long[2 * t + 1] : -1);
+  d->n_long_pairs = (int64_t)h_long_pairs.size();
 
   auto alloc_fail = [&](hipError_t err, const char* what) {
     destroy_db(h);
@@ -832,6 +876,8 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   if ((e = d->res.reserve((size_t)d->n_res)) != hipSuccess) return alloc_fail(e, "residues");
   if ((e = d->offs.reserve((size_t)n_seqs + 1)) != hipSuccess) return alloc_fail(e, "offsets");
   if ((e = d->d_long_items.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
+  if ((e = d->d_long_pairs.reserve(h_long_pairs.size())) != hipSuccess)
+    return alloc_fail(e, "long pairs");
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -841,7 +887,8 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
       (e = up(d->slot_seq.p, h_slots.data(), h_slots.size() * 4)) != hipSuccess ||
       (e = up(d->res.p, residues, (size_t)d->n_res)) != hipSuccess ||
       (e = up(d->offs.p, offsets, ((size_t)n_seqs + 1) * 8)) != hipSuccess ||
-      (e = up(d->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess) {
+      (e = up(d->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess ||
+      (e = up(d->d_long_pairs.p, h_long_pairs.data(), h_long_pairs.size() * 8)) != hipSuccess) {
     destroy_db(h);
     return hip_fail(e, "database upload");
   }
@@ -1071,7 +1118,7 @@ static int impl_get_stats(swdb::Searcher* db, sw_stats* out) {
   db->timed.clear();
   int32_t cnt = 0;
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
-  if (db->flags.p && db->d->plan.n_bins > 0) {
+  if (db->flags.p && (db->d->plan.n_bins > 0 || db->d->plan.n_long > 0)) {
     if ((e = hipMemcpy(&cnt, db->flags.p, 4, hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "stats");
   }
@@ -1280,9 +1327,8 @@ void sw_ctx_free(sw_ctx* c) {
 int64_t sw_ctx_bytes(const sw_db* h) {
   if (!h) return -1;
   const swdb::Plan& P = h->data.plan;
-  return P.boundary_uint4 * 16 +
-         (int64_t)swdb::kIntraGridRescore * std::max<int32_t>(P.max_all_bin_len, 1) * 8 +
-         (2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS, 1)) * 4;
+  return P.boundary_uint4 * 16 + (int64_t)swdb::kIntraGridRescore * swdb::rescore_stride(P) * 8 +
+         (2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)) * 4;
 }
 
 int sw_ctx_search_async(sw_ctx* c, const uint8_t* d_query, int32_t query_len,

@@ -105,13 +105,15 @@ def test_forced_rescoring(sw, limit):
         t_long = sw.SW_DEFAULT_LONG_THRESHOLD
     want = _oracle(q, res, offs)
     assert (got == want).all()
-    in_bins = lens < t_long          # the long list is always scored in 32 bits
+    # both packed kernels (bins and the long list) hand scores at or above the
+    # limit to the 32-bit rescoring; the exact range of binary16 ends at 2048
+    assert (lens >= t_long).any()
     if limit == 0:
-        assert st["n_rescored"] == int(in_bins.sum())
+        assert st["n_rescored"] == len(lens)
     if limit == 40:
-        assert st["n_rescored"] == int((want[in_bins] >= 40).sum())
-    if limit == 32767:               # the half-precision kernels' exact range ends at 2048
-        assert st["n_rescored"] == int((want[in_bins] >= 2048).sum())
+        assert st["n_rescored"] == int((want >= 40).sum())
+    if limit == 32767:
+        assert st["n_rescored"] == int((want >= 2048).sum())
 
 
 def test_scores_around_the_half_precision_limit(sw):
@@ -136,18 +138,23 @@ def test_scores_around_the_half_precision_limit(sw):
     want = _oracle(q, res, offs)
     assert ((want >= 1800) & (want < 2048)).any() and (want > 2048).sum() >= 3
     qs = [q, q[20:].copy(), swinputs.random_residues(90, rng)]
-    say("half-precision limit")
-    with sw.Database(res, offs, long_threshold=10**6) as db:
-        got = db.search(q, B62, 10, 2)
-        st = db.stats()
-        gotb = db.search_batch(qs, B62, 10, 2)
-        stb = db.stats()
-    assert (got == want).all()
-    assert st["n_rescored"] == int((want >= 2048).sum())
     wants = [_oracle(x, res, offs) for x in qs]
-    for row, wq in zip(gotb, wants):
-        assert (row == wq).all()
-    assert stb["n_rescored"] == sum(int((wq >= 2048).sum()) for wq in wants)
+    # all in bins; then the planted ones (>= 257 residues) in the long list,
+    # scored by the packed intra-task kernel (batched: long bins)
+    for t_long in (10**6, 250):
+        say("half-precision limit, long threshold %d" % t_long)
+        with sw.Database(res, offs, long_threshold=t_long) as db:
+            if t_long == 250:
+                assert db.info()["n_long"] >= 9
+            got = db.search(q, B62, 10, 2)
+            st = db.stats()
+            gotb = db.search_batch(qs, B62, 10, 2)
+            stb = db.stats()
+        assert (got == want).all()
+        assert st["n_rescored"] == int((want >= 2048).sum())
+        for row, wq in zip(gotb, wants):
+            assert (row == wq).all()
+        assert stb["n_rescored"] == sum(int((wq >= 2048).sum()) for wq in wants)
 
 
 def test_planted_overflow_in_short_bins(sw):
