@@ -191,6 +191,8 @@ hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_
   if (R == r && W == w) return launch_rw<r, w>(n_bins, a, s);
   SWDB_CASE(16, 1) SWDB_CASE(16, 2) SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12)
   SWDB_CASE(32, 1) SWDB_CASE(32, 2) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(20, 12) SWDB_CASE(22, 12)
+  SWDB_CASE(24, 12)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }

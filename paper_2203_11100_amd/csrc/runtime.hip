@@ -304,14 +304,30 @@ int tune_bucket(int m) {
 // every query length of the plain workload and for the batched one).
 constexpr int kDefaultRows = 16, kDefaultWaves = 12;
 
-int pick_rows(const Searcher* db, int m) {
-  if (db->opt_rows) return db->opt_rows;
-  if (db->tune_rows[tune_bucket(m)]) return db->tune_rows[tune_bucket(m)];
-  return kDefaultRows;
+// Strip height for 12-wave workgroups: the height in {12, 14, ..., 20} with
+// the smallest ceil(ceil(m / R) / 12) x (34 R + 96), the rounds a bin takes
+// times the time of a 4-column chunk: 34 VALU per row (4 columns x 8.5) and
+// a fixed part (23 VALU of loop overhead plus barrier and latency stalls)
+// fitted to the measured rates of 16- and 20-row strips on long queries.
+// Ties go to the taller strip.
+int fit_rows(int m) {
+  int best_r = kDefaultRows;
+  int64_t best = INT64_MAX;
+  for (int R : {20, 18, 16, 14, 12}) {
+    const int64_t rounds = ((m + R - 1) / R + 11) / 12;
+    const int64_t cost = rounds * (34 * R + 96);
+    if (cost < best) { best = cost; best_r = R; }
+  }
+  return best_r;
 }
 
-int pick_waves(const Searcher* db, int n_strips, int m) {
-  (void)n_strips;
+int pick_rows(const Searcher* db, int m, int W) {
+  if (db->opt_rows) return db->opt_rows;
+  if (db->tune_rows[tune_bucket(m)]) return db->tune_rows[tune_bucket(m)];
+  return W == 12 ? fit_rows(m) : kDefaultRows;
+}
+
+int pick_waves(const Searcher* db, int m) {
   if (db->opt_waves) return db->opt_waves;
   if (db->tune_waves[tune_bucket(m)]) return db->tune_waves[tune_bucket(m)];
   return kDefaultWaves;
@@ -413,11 +429,12 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     e = launch_fill(d_out, db->d->n_seqs, 0, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "fill");
   }
-  const int R = pick_rows(db, m);
+  int W = pick_waves(db, m);
+  int R = pick_rows(db, m, W);
+  if (W == 12 && R == 32) W = 8;              // 32-row strips have no 12-wave form
+  if (W != 12 && R != 16 && R != 32) R = 16;  // heights 12..20 exist with 12 waves only
   const int m_pad = (m + R - 1) / R * R;
   const int n_strips = m_pad / R;
-  int W = pick_waves(db, n_strips, m);
-  if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
   const int64_t n_long = db->d->plan.n_long;
   int RR = 8, W2 = 1, RRr = 8, W2r = 1;
   pick_intra(db, m, 8, &RR, &W2, true);   // long sequences, in pairs (binary16)
@@ -553,7 +570,7 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
       if (db->tune_brows[b]) { R = db->tune_brows[b]; W = db->tune_bwaves[b]; }
     }
   }
-  if (db->opt_rows) R = db->opt_rows;
+  if (db->opt_rows == 16 || db->opt_rows == 32) R = db->opt_rows;
   if (db->opt_waves == 4 || db->opt_waves == 8 || db->opt_waves == 12) W = db->opt_waves;
   if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
   std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
@@ -1063,7 +1080,9 @@ static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
       db->sat_limit = (int32_t)value;
       return SW_OK;
     case SW_OPT_ROWS:
-      if (value != 0 && value != 16 && value != 32) return fail(SW_EINVAL, "rows must be 0, 16 or 32");
+      if (value != 0 && value != 12 && value != 14 && value != 16 && value != 18 && value != 20 &&
+          value != 32)
+        return fail(SW_EINVAL, "rows must be 0, 12, 14, 16, 18, 20 or 32");
       db->opt_rows = (int32_t)value;
       return SW_OK;
     case SW_OPT_WAVES:
@@ -1140,7 +1159,8 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
   DeviceGuard g(db->d->device);
   if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) return SW_OK;
   static const int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
-  static const int cand_r[SW_TUNE_CANDIDATES] = {16, 16, 32, 32};
+  // rows 0: fitted to each query's length (single queries), 16 (batched)
+  static const int cand_r[SW_TUNE_CANDIDATES] = {16, 0, 32, 32};
   static const int cand_w[SW_TUNE_CANDIDATES] = {8, 12, 4, 8};
   hipError_t e;
   hipStream_t s = db->own_stream;
