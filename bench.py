@@ -158,7 +158,7 @@ def main():
             "traffic": measured_traffic(st["rows"], st["waves"]),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, mean over the "
                             "step's 20 launches)",
-            "kernel": "k_inter_i16 (rows %d, waves %d)" % (st["rows"], st["waves"]),
+            "kernel": "k_inter_f16 (rows %d, waves %d)" % (st["rows"], st["waves"]),
             "avg_launch_ms": st["ms_inter"] / n_launch,
             "ops_per_cell": OPS_PER_CELL}
     result = {

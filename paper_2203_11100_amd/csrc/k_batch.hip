@@ -24,7 +24,7 @@ namespace swdb {
 namespace {
 
 template <int R, int W>
-__global__ __launch_bounds__(64 * W) void k_batch_i16(BatchArgs a) {
+__global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
   constexpr int D = 2;   // superstep skew between consecutive waves
   constexpr int kSlot = R * kBatchRowDwords;
   constexpr int kStage = (kSlot + 63) / 64;
@@ -158,14 +158,14 @@ __global__ __launch_bounds__(64 * W) void k_batch_i16(BatchArgs a) {
 
 template <int R, int W>
 hipError_t launch_rw(int grid, const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_i16<R, W>), dim3(grid), dim3(64 * W), 0, s, a);
+  hipLaunchKernelGGL((k_batch_f16<R, W>), dim3(grid), dim3(64 * W), 0, s, a);
   return hipGetLastError();
 }
 
 template <int R, int W>
 int occupancy() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_batch_i16<R, W>),
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_batch_f16<R, W>),
                                                    64 * W, 0) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;

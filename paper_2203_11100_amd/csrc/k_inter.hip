@@ -44,7 +44,7 @@ namespace swdb {
 namespace {
 
 template <int R, int W>
-__global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
+__global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   constexpr int D = 2;   // superstep skew between consecutive waves
   constexpr int kSlot = R * kProfRowDwords;
   constexpr int kStage = (kSlot + 63) / 64;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_i16(InterArgs a) {
 
 template <int R, int W>
 hipError_t launch_rw(int n_bins, const InterArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_inter_i16<R, W>), dim3(n_bins), dim3(64 * W), 0, s, a);
+  hipLaunchKernelGGL((k_inter_f16<R, W>), dim3(n_bins), dim3(64 * W), 0, s, a);
   return hipGetLastError();
 }
 

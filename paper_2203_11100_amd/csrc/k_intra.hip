@@ -237,7 +237,7 @@ __device__ __forceinline__ uint32_t pv_get(const uint4& v, int j) {
 // code row, a's in the low and b's in the high 16 bits of one register.
 // Sequences whose maximum reaches the limit go to the rescoring list.
 template <int R, int W2>
-__global__ __launch_bounds__(64 * W2) void k_intra_h2(IntraPairArgs a) {
+__global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
   constexpr int ROWS = 64 * R;        // query rows per pass
   constexpr int RP = R / 2;           // row-pair dwords per lane and code
   constexpr int CODE_DW = ROWS / 2;   // dwords per code row of a pass
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(64 * W2) void k_intra_h2(IntraPairArgs a) {
 
 template <int R, int W2>
 hipError_t launch_pair_rw(int grid, const IntraPairArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_intra_h2<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
+  hipLaunchKernelGGL((k_intra_f16<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
   return hipGetLastError();
 }
 
