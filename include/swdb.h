@@ -153,13 +153,15 @@ enum sw_option {
                              reaches min(limit, 2048) is rescored in 32-bit
                              integers (default 32767, i.e. the whole exact
                              range; 0 rescores everything) */
-  SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto: with 12
-                             waves, the height in 12..20 that best fills the
-                             waves' rounds for the query length), 12, 14, 16,
-                             18, 20 (12 waves only; 16 otherwise), 32 (not
-                             with 12 waves); batched searches use 16 or 32 */
-  SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12
-                             (12 not with 32 rows) */
+  SW_OPT_ROWS = 3,        /* inter-task query rows per strip: 0 (auto: rows and
+                             waves fitted to the query length from the
+                             schedules' measured efficiencies), 12, 14, 16,
+                             18, 20 (with 12 waves; 12 and 14 also with 16;
+                             16 otherwise), 32 (not with 12 or 16 waves);
+                             batched searches use 16 or 32 */
+  SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12,
+                             16 (12 not with 32 rows; 16 with 12 or 14 rows,
+                             four waves per SIMD; batched searches: 4, 8, 12) */
   SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
   SW_OPT_INTRA_WAVES = 6, /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
   SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph
@@ -197,8 +199,8 @@ int sw_get_stats(sw_db* db, sw_stats* out);
  * around the kernels, and keeps the candidate with the highest GCUPS.
  * Later searches on the handle (and contexts created afterwards) use the
  * tuned entry of their query's bucket unless SW_OPT_ROWS / SW_OPT_WAVES are
- * set.  A candidate with 0 rows has its strip height fitted to each query's
- * length (single queries; 16 rows in batched searches).  Takes about a second on a 200,000-sequence database.  `report` may
+ * set.  The candidate (0, 0) is the schedule fitted to each query's length
+ * (single queries; 16 rows and 12 waves in batched searches).  Takes about a second on a 200,000-sequence database.  `report` may
  * be NULL.  Errors leave the handle untuned. */
 #define SW_TUNE_BUCKETS 4
 #define SW_TUNE_CANDIDATES 4

@@ -56,9 +56,14 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   const BinDesc bin = a.bins[a.bin_begin + blockIdx.x];
   const int C = (int)(bin.len >> 2);
   const int S = a.n_strips;
-  const int q_last = (S - 1) / W, w_last = (S - 1) % W;
+  // waves in use: the wrap from the last wave of a round to the first of the
+  // next needs C >= D * (Wu - 1) + 2 chunks (see below), so a bin shorter
+  // than that leaves the top waves idle (never with 12 waves: every bin has
+  // at least SW_MIN_BIN_LEN / 4 = 24 chunks)
+  const int Wu = __builtin_amdgcn_readfirstlane(min(W, C / D));
+  const int q_last = (S - 1) / Wu, w_last = (S - 1) % Wu;
   const int T_total = q_last * C + D * w_last + C;
-  const int my_rounds = (w < S) ? (S - 1 - w) / W + 1 : 0;
+  const int my_rounds = (w < S && w < Wu) ? (S - 1 - w) / Wu + 1 : 0;
 
   if (my_rounds > 0) {
     const uint32_t* src = a.prof + (size_t)w * kSlot;
@@ -94,15 +99,18 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   // strips back to back, then idles until the last wave finishes; every wave
   // passes T_total barriers.  With the skew D = 2, the chunk a wave prefetches
   // in superstep T was written by the previous strip's wave in T-1 or
-  // earlier (bins have at least 2W chunks, which covers the wrap from the
-  // last wave to the first).
+  // earlier; for the wrap from the last wave to the first that needs
+  // C >= D * (Wu - 1) + 2, which is how Wu is chosen.
+  // Every wave passes exactly T_total barriers: its lead-in (all of T_total
+  // for an idle wave), my_rounds * C supersteps of work, then the tail.
+  const int lead = min(D * w, T_total);
   if (w == 0 && my_rounds > 0) fetch(0, 0);
-  for (int T = 0; T < D * w; ++T) {
+  for (int T = 0; T < lead; ++T) {
     if (T == D * w - 1 && my_rounds > 0) fetch(w, 0);
     __syncthreads();
   }
   for (int q = 0; q < my_rounds; ++q) {
-    const int s = q * W + w;
+    const int s = q * Wu + w;
 #pragma unroll
     for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
     uint32_t hdiag = 0;
@@ -113,12 +121,12 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
       const uint32_t up_h[4] = {b0_n.x, b0_n.z, b1_n.x, b1_n.z};
       const uint32_t up_f[4] = {b0_n.y, b0_n.w, b1_n.y, b1_n.w};
       if (c + 1 < C) fetch(s, c + 1);
-      else if (more) fetch(s + W, 0);
+      else if (more) fetch(s + Wu, 0);
       // next strip's profile: global loads now, LDS stores after the compute
       const bool stage = more && c == C - 1;
       uint32_t st[kStage];
       if (stage) {
-        const uint32_t* src = a.prof + (size_t)(s + W) * kSlot;
+        const uint32_t* src = a.prof + (size_t)(s + Wu) * kSlot;
 #pragma unroll
         for (int x = 0; x < kStage; ++x)
           if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
       __syncthreads();
     }
   }
-  for (int T = D * w + my_rounds * C; T < T_total; ++T) __syncthreads();
+  for (int T = lead + my_rounds * C; T < T_total; ++T) __syncthreads();
 
   lbest[w][lane] = best;
   __syncthreads();
@@ -191,8 +199,8 @@ hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_
   if (R == r && W == w) return launch_rw<r, w>(n_bins, a, s);
   SWDB_CASE(16, 1) SWDB_CASE(16, 2) SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12)
   SWDB_CASE(32, 1) SWDB_CASE(32, 2) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
-  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(20, 12) SWDB_CASE(22, 12)
-  SWDB_CASE(24, 12)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(20, 12)
+  SWDB_CASE(12, 16) SWDB_CASE(14, 16)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }

@@ -304,33 +304,52 @@ int tune_bucket(int m) {
 // every query length of the plain workload and for the batched one).
 constexpr int kDefaultRows = 16, kDefaultWaves = 12;
 
-// Strip height for 12-wave workgroups: the height in {12, 14, ..., 20} with
-// the smallest ceil(ceil(m / R) / 12) x (34 R + 96), the rounds a bin takes
-// times the time of a 4-column chunk: 34 VALU per row (4 columns x 8.5) and
-// a fixed part (23 VALU of loop overhead plus barrier and latency stalls)
-// fitted to the measured rates of 16- and 20-row strips on long queries.
-// Ties go to the taller strip.
-int fit_rows(int m) {
-  int best_r = kDefaultRows;
-  int64_t best = INT64_MAX;
-  for (int R : {20, 18, 16, 14, 12}) {
-    const int64_t rounds = ((m + R - 1) / R + 11) / 12;
-    const int64_t cost = rounds * (34 * R + 96);
-    if (cost < best) { best = cost; best_r = R; }
+// The fitted schedules of the single-query inter-task kernel: strip height
+// R and waves W with the fraction of the packed VALU peak each sustains per
+// strip slot, measured on the plain workload's three longest queries (where
+// every schedule fills its rounds): 12 waves (3 per SIMD) with 12..20 rows,
+// 16 waves (4 per SIMD, <= 128 VGPRs) with 12 or 14 rows.
+struct Sched {
+  int R, W;
+  double eff;
+};
+constexpr Sched kScheds[] = {{20, 12, 0.849}, {18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
+                             {12, 12, 0.781}, {14, 16, 0.868}, {12, 16, 0.832}};
+
+// A bin of C chunks takes ceil(S / W) rounds of its S = ceil(m / R) strips,
+// each round C supersteps of W waves' chunks, so its time is proportional
+// to ceil(S / W) * W * R / eff.  Picks the schedule minimising that among
+// those with the given rows / waves (0: any); false if none matches.
+bool fit_schedule(int m, int rows, int waves, int* R_out, int* W_out) {
+  double best = 1e300;
+  for (const Sched& c : kScheds) {
+    if ((rows && c.R != rows) || (waves && c.W != waves)) continue;
+    const int64_t rounds = ((m + c.R - 1) / c.R + c.W - 1) / c.W;
+    const double cost = (double)rounds * c.W * c.R / c.eff;
+    if (cost < best) { best = cost; *R_out = c.R; *W_out = c.W; }
   }
-  return best_r;
+  return best < 1e300;
 }
 
-int pick_rows(const Searcher* db, int m, int W) {
-  if (db->opt_rows) return db->opt_rows;
-  if (db->tune_rows[tune_bucket(m)]) return db->tune_rows[tune_bucket(m)];
-  return W == 12 ? fit_rows(m) : kDefaultRows;
-}
-
-int pick_waves(const Searcher* db, int m) {
-  if (db->opt_waves) return db->opt_waves;
-  if (db->tune_waves[tune_bucket(m)]) return db->tune_waves[tune_bucket(m)];
-  return kDefaultWaves;
+// Schedule of a single search: both options, else the autotuned entry of
+// the query's bucket, else the fitted schedule (within a set option).
+void pick_schedule(const Searcher* db, int m, int* R_out, int* W_out) {
+  int R = db->opt_rows, W = db->opt_waves;
+  const int b = tune_bucket(m);
+  if (!(R && W)) {
+    if (!R && !W && db->tune_waves[b]) {
+      R = db->tune_rows[b];
+      W = db->tune_waves[b];
+    } else if (!fit_schedule(m, R, W, &R, &W)) {
+      if (!R) R = kDefaultRows;
+      if (!W) W = (R == 32) ? 8 : kDefaultWaves;
+    }
+  }
+  if (W == 12 && R == 32) W = 8;                                 // no 12-wave form of 32 rows
+  if (W == 16 && R != 12 && R != 14) fit_schedule(m, 0, 16, &R, &W);  // 16 waves: 12, 14
+  if (W != 12 && W != 16 && R != 16 && R != 32) R = 16;          // 12..20 rows: 12 or 16 waves
+  *R_out = R;
+  *W_out = W;
 }
 
 // Rows per lane (R) and waves (W2) of the intra-task kernel for a query of
@@ -429,10 +448,8 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     e = launch_fill(d_out, db->d->n_seqs, 0, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "fill");
   }
-  int W = pick_waves(db, m);
-  int R = pick_rows(db, m, W);
-  if (W == 12 && R == 32) W = 8;              // 32-row strips have no 12-wave form
-  if (W != 12 && R != 16 && R != 32) R = 16;  // heights 12..20 exist with 12 waves only
+  int R = kDefaultRows, W = kDefaultWaves;
+  pick_schedule(db, m, &R, &W);
   const int m_pad = (m + R - 1) / R * R;
   const int n_strips = m_pad / R;
   const int64_t n_long = db->d->plan.n_long;
@@ -1086,8 +1103,9 @@ static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
       db->opt_rows = (int32_t)value;
       return SW_OK;
     case SW_OPT_WAVES:
-      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 12)
-        return fail(SW_EINVAL, "waves must be 0, 1, 2, 4, 8 or 12");
+      if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8 && value != 12 &&
+          value != 16)
+        return fail(SW_EINVAL, "waves must be 0, 1, 2, 4, 8, 12 or 16");
       db->opt_waves = (int32_t)value;
       return SW_OK;
     case SW_OPT_INTRA_ROWS:
@@ -1159,9 +1177,10 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
   DeviceGuard g(db->d->device);
   if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) return SW_OK;
   static const int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
-  // rows 0: fitted to each query's length (single queries), 16 (batched)
+  // (0, 0): the fitted schedule of each query length (single queries),
+  // 16 rows and 12 waves (batched)
   static const int cand_r[SW_TUNE_CANDIDATES] = {16, 0, 32, 32};
-  static const int cand_w[SW_TUNE_CANDIDATES] = {8, 12, 4, 8};
+  static const int cand_w[SW_TUNE_CANDIDATES] = {8, 0, 4, 8};
   hipError_t e;
   hipStream_t s = db->own_stream;
   Matrix mat{};

@@ -64,7 +64,8 @@ def test_ragged_database_query_lengths(sw, m):
 
 @pytest.mark.parametrize("rows,waves", [(16, 1), (16, 2), (16, 4), (16, 8), (16, 12),
                                         (32, 1), (32, 2), (32, 4), (32, 8),
-                                        (12, 12), (14, 12), (18, 12), (20, 12)])
+                                        (12, 12), (14, 12), (18, 12), (20, 12),
+                                        (12, 16), (14, 16)])
 def test_strip_and_wave_options(sw, rows, waves):
     res, offs = _ragged_db(1)
     q = swinputs.random_residues(333, np.random.default_rng(5))
@@ -78,29 +79,34 @@ def test_strip_and_wave_options(sw, rows, waves):
     assert (got == _oracle(q, res, offs)).all()
 
 
-def _fit_rows(m):
-    """The strip height the library fits to a query with 12 waves: the
-    fewest rounds x (34 R + 96), ties to the taller strip."""
+# (rows, waves, efficiency per strip slot) of the library's fitted schedules
+_SCHEDS = [(20, 12, 0.849), (18, 12, 0.851), (16, 12, 0.830), (14, 12, 0.812),
+           (12, 12, 0.781), (14, 16, 0.868), (12, 16, 0.832)]
+
+
+def _fit_schedule(m):
+    """The schedule the library fits to a query: the fewest
+    ceil(strips / W) * W * R / efficiency, first listed on ties."""
     best = None
-    for R in (20, 18, 16, 14, 12):
+    for R, W, eff in _SCHEDS:
         strips = -(-m // R)
-        cost = -(-strips // 12) * (34 * R + 96)
+        cost = -(-strips // W) * W * R / eff
         if best is None or cost < best[0]:
-            best = (cost, R)
-    return best[1]
+            best = (cost, R, W)
+    return best[1], best[2]
 
 
-@pytest.mark.parametrize("m", [1, 13, 144, 211, 256, 310, 454, 977, 1184])
-def test_fitted_strip_height(sw, m):
-    """Without options, 12-wave searches take the fitted strip height and
-    stay exact (the heights have ragged last strips of various sizes)."""
+@pytest.mark.parametrize("m", [1, 13, 144, 211, 256, 310, 454, 666, 977, 1184, 1736])
+def test_fitted_schedule(sw, m):
+    """Without options a search takes the fitted (rows, waves) and stays
+    exact (ragged last strips, 16-wave bins shorter than 32 chunks)."""
     res, offs = _ragged_db(40)
     q = swinputs.random_residues(m, np.random.default_rng(41))
-    say("fitted rows m=%d" % m)
+    say("fitted schedule m=%d" % m)
     with sw.Database(res, offs) as db:
         got = db.search(q, B62, 10, 2)
         st = db.stats()
-    assert st["waves"] == 12 and st["rows"] == _fit_rows(m)
+    assert (st["rows"], st["waves"]) == _fit_schedule(m)
     assert (got == _oracle(q, res, offs)).all()
 
 
@@ -427,8 +433,8 @@ def test_autotune_then_searches_stay_exact(sw):
         rep = db.autotune()
         assert len(rep["buckets"]) == 4
         for b in rep["buckets"]:
-            assert b["chosen"] in [(16, 8), (0, 12), (32, 4), (32, 8)]
-            assert b["batch_chosen"] in [(16, 8), (0, 12), (32, 4), (32, 8)]
+            assert b["chosen"] in [(16, 8), (0, 0), (32, 4), (32, 8)]
+            assert b["batch_chosen"] in [(16, 8), (0, 0), (32, 4), (32, 8)]
             assert max(b["gcups"].values()) > 0 and max(b["batch_gcups"].values()) > 0
         single = [db.search(q, B62, 10, 2) for q in qs]
         batch = db.search_batch(qs, B62, 10, 2)
