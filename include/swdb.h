@@ -158,10 +158,13 @@ enum sw_option {
                              schedules' measured efficiencies), 12, 14, 16,
                              18, 20 (with 12 waves; 12 and 14 also with 16;
                              16 otherwise), 32 (not with 12 or 16 waves);
-                             batched searches use 16 or 32 */
+                             batched searches: 12, 14, 16, 18 with 12 waves,
+                             12 with 16, 16 or 32 otherwise, auto fitted to
+                             the pairs' lengths */
   SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12,
                              16 (12 not with 32 rows; 16 with 12 or 14 rows,
-                             four waves per SIMD; batched searches: 4, 8, 12) */
+                             four waves per SIMD; batched searches: 4, 8, 12,
+                             16) */
   SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
   SW_OPT_INTRA_WAVES = 6, /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
   SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph

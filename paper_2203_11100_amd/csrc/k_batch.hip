@@ -50,9 +50,13 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
     const int half = iv.y & 1;
     const int C = (int)(bin.len >> 2);
     const int S = pd.n_strips;
-    const int q_last = (S - 1) / W, w_last = (S - 1) % W;
+    // waves in use: the wrap from a round's last wave to the next round's
+    // first needs C >= D * (Wu - 1) + 2 chunks (16 waves: shorter bins
+    // leave the top waves idle; see k_inter.hip)
+    const int Wu = __builtin_amdgcn_readfirstlane(min(W, C / D));
+    const int q_last = (S - 1) / Wu, w_last = (S - 1) % Wu;
     const int T_total = q_last * C + D * w_last + C;
-    const int my_rounds = (w < S) ? (S - 1 - w) / W + 1 : 0;
+    const int my_rounds = (w < S && w < Wu) ? (S - 1 - w) / Wu + 1 : 0;
     const uint32_t* __restrict__ prof = a.prof + pd.prof_off;
     // lane's residues: dword res_off + c*128 + 2*lane + half
     const uint32_t* __restrict__ rlane = a.res + bin.res_off + 2 * lane + half;
@@ -81,13 +85,15 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
 
     uint32_t H[R], E[R];
     uint32_t best = 0;
+    // every wave passes exactly T_total barriers (idle waves: all lead-in)
+    const int lead = min(D * w, T_total);
     if (w == 0 && my_rounds > 0) fetch(0, 0);
-    for (int T = 0; T < D * w; ++T) {
+    for (int T = 0; T < lead; ++T) {
       if (T == D * w - 1 && my_rounds > 0) fetch(w, 0);
       __syncthreads();
     }
     for (int q = 0; q < my_rounds; ++q) {
-      const int s = q * W + w;
+      const int s = q * Wu + w;
 #pragma unroll
       for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
       uint32_t hdiag = 0;
@@ -98,11 +104,11 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
         const uint32_t up_h[4] = {b_n.x, b_n.z, b_n2.x, b_n2.z};
         const uint32_t up_f[4] = {b_n.y, b_n.w, b_n2.y, b_n2.w};
         if (c + 1 < C) fetch(s, c + 1);
-        else if (more) fetch(s + W, 0);
+        else if (more) fetch(s + Wu, 0);
         const bool stage = more && c == C - 1;
         uint32_t st[kStage];
         if (stage) {
-          const uint32_t* src = prof + (size_t)(s + W) * kSlot;
+          const uint32_t* src = prof + (size_t)(s + Wu) * kSlot;
 #pragma unroll
           for (int x = 0; x < kStage; ++x)
             if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
@@ -129,7 +135,7 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
         __syncthreads();
       }
     }
-    for (int T = D * w + my_rounds * C; T < T_total; ++T) __syncthreads();
+    for (int T = lead + my_rounds * C; T < T_total; ++T) __syncthreads();
 
     lbest[w][lane] = best;
     __syncthreads();
@@ -178,6 +184,7 @@ hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t 
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return launch_rw<r, w>(grid, a, s);
   SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(12, 16)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }
@@ -186,6 +193,7 @@ int batch_workgroups_per_cu(int R, int W) {
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return occupancy<r, w>();
   SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(12, 16)
 #undef SWDB_CASE
   return 1;
 }

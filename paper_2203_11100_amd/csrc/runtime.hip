@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -316,6 +317,11 @@ struct Sched {
 constexpr Sched kScheds[] = {{20, 12, 0.849}, {18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
                              {12, 12, 0.781}, {14, 16, 0.868}, {12, 16, 0.832}};
 
+// The batched kernel's fitted schedules (the 20 x 12 and 14 x 16 forms
+// spill registers there); efficiencies taken from the single-query table.
+constexpr Sched kBatchScheds[] = {{18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
+                                  {12, 12, 0.781}, {12, 16, 0.832}};
+
 // A bin of C chunks takes ceil(S / W) rounds of its S = ceil(m / R) strips,
 // each round C supersteps of W waves' chunks, so its time is proportional
 // to ceil(S / W) * W * R / eff.  Picks the schedule minimising that among
@@ -575,21 +581,42 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
                   const Matrix& mat, int32_t go, int32_t ge, int32_t* d_out) {
   BatchPlan& B = db->batch;
   // schedule: options, else the autotuned entry of the median query length,
-  // else the default
+  // else the one fitted to the pairs' lengths
   int R = kDefaultRows, W = kDefaultWaves;
   {
     std::vector<int64_t> lens;
     for (int32_t q = 0; q < nq; ++q)
       if (qoffs[q + 1] > qoffs[q]) lens.push_back(qoffs[q + 1] - qoffs[q]);
+    std::sort(lens.begin(), lens.end(), std::greater<int64_t>());
+    bool tuned = false;
     if (!lens.empty()) {
-      std::nth_element(lens.begin(), lens.begin() + lens.size() / 2, lens.end());
       const int b = tune_bucket((int)lens[lens.size() / 2]);
-      if (db->tune_brows[b]) { R = db->tune_brows[b]; W = db->tune_bwaves[b]; }
+      if (db->tune_brows[b]) { R = db->tune_brows[b]; W = db->tune_bwaves[b]; tuned = true; }
+    }
+    if (!tuned && !lens.empty()) {
+      // a pair of neighbouring lengths costs ceil(S / W) rounds of its
+      // S = ceil(m / R) strips (m the longer query) for every half bin
+      double best = 1e300;
+      for (const Sched& c : kBatchScheds) {
+        if ((db->opt_rows && c.R != db->opt_rows) || (db->opt_waves && c.W != db->opt_waves))
+          continue;
+        double cost = 0;
+        for (size_t i = 0; i < lens.size(); i += 2) {
+          const int64_t strips = (lens[i] + c.R - 1) / c.R;
+          cost += (double)((strips + c.W - 1) / c.W) * c.W * c.R / c.eff;
+        }
+        if (cost < best) { best = cost; R = c.R; W = c.W; }
+      }
     }
   }
-  if (db->opt_rows == 16 || db->opt_rows == 32) R = db->opt_rows;
-  if (db->opt_waves == 4 || db->opt_waves == 8 || db->opt_waves == 12) W = db->opt_waves;
-  if (W == 12 && R != 16) W = 8;   // 12 waves exist for 16-row strips only
+  if (db->opt_rows == 12 || db->opt_rows == 14 || db->opt_rows == 16 || db->opt_rows == 18 ||
+      db->opt_rows == 32)
+    R = db->opt_rows;
+  if (db->opt_waves == 4 || db->opt_waves == 8 || db->opt_waves == 12 || db->opt_waves == 16)
+    W = db->opt_waves;
+  if (W == 16 && R != 12) R = 12;                  // 16 waves: 12-row strips
+  if (W == 12 && R == 32) W = 8;                   // no 12-wave form of 32 rows
+  if (W != 12 && W != 16 && R != 16 && R != 32) R = 16;
   std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
   if (B.valid && B.qoffs == qv && memcmp(&B.mat, &mat, sizeof(mat)) == 0 && B.go == go &&
       B.ge == ge && B.d_queries == d_queries && B.d_out == d_out && B.R == R && B.W == W &&
@@ -1212,6 +1239,10 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
   db->use_graphs = false;
   sw_tune_report local{};
   int rc = SW_OK;
+  // untuned while measuring, so the fitted candidate (0, 0) is what it says
+  for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
+    db->tune_rows[b] = db->tune_waves[b] = db->tune_brows[b] = db->tune_bwaves[b] = 0;
+  int pick[SW_TUNE_BUCKETS] = {}, bpick[SW_TUNE_BUCKETS] = {};
   for (int b = 0; b < SW_TUNE_BUCKETS && rc == SW_OK; ++b) {
     const int m = rep_len[b];
     local.query_len[b] = m;
@@ -1236,7 +1267,7 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
       db->timed.clear();
       const double gc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
       local.gcups[b][c] = (float)gc;
-      if (gc > best) { best = gc; db->tune_rows[b] = cand_r[c]; db->tune_waves[b] = cand_w[c]; }
+      if (gc > best) { best = gc; pick[b] = c; }
       // batched: one pair of queries of this length
       const int64_t qo[3] = {0, m, 2 * (int64_t)m};
       db->stats = sw_stats{};
@@ -1256,12 +1287,18 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
       db->timed.clear();
       const double bgc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
       local.batch_gcups[b][c] = (float)bgc;
-      if (bgc > bbest) { bbest = bgc; db->tune_brows[b] = cand_r[c]; db->tune_bwaves[b] = cand_w[c]; }
+      if (bgc > bbest) { bbest = bgc; bpick[b] = c; }
     }
-    local.rows[b] = db->tune_rows[b];
-    local.waves[b] = db->tune_waves[b];
-    local.batch_rows[b] = db->tune_brows[b];
-    local.batch_waves[b] = db->tune_bwaves[b];
+    local.rows[b] = cand_r[pick[b]];
+    local.waves[b] = cand_w[pick[b]];
+    local.batch_rows[b] = cand_r[bpick[b]];
+    local.batch_waves[b] = cand_w[bpick[b]];
+  }
+  for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
+    db->tune_rows[b] = local.rows[b];
+    db->tune_waves[b] = local.waves[b];
+    db->tune_brows[b] = local.batch_rows[b];
+    db->tune_bwaves[b] = local.batch_waves[b];
   }
   (void)hipStreamSynchronize(s);
   db->batch.release();
