@@ -35,8 +35,8 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection sources it was taken on:
 # bench reports null when their digest differs.
-TRAFFIC = {"bytes_per_launch": 1.7594e+10, "fetch_bytes": 49.28e9, "write_bytes": 302.61e9,
-           "launches": 20, "sources_sha256": "05b72f738b73b1d4ba06be47ab7a6bb3c672f492c636e012295fe55ef538e3af"}
+TRAFFIC = {"bytes_per_launch": 1.7627e+10, "fetch_bytes": 49.70e9, "write_bytes": 302.84e9,
+           "launches": 20, "sources_sha256": "e35271ecc465a805748df8d9e9c6c82f86310be111f030dee7d7cfbe4eef24fe"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
 # instruction x 2.4 GHz = 78.64 T half-ops/s

@@ -247,6 +247,25 @@ def test_empty_query_and_empty_database(sw):
         assert db.search(swinputs.encode("ACDE"), B62, 10, 2).shape == (0,)
 
 
+def test_very_long_query_and_sequence(sw):
+    """A 40,000-residue query (2,858 strips of 14) against bins and a long
+    list holding a 60,000-residue sequence, single and batched: exact."""
+    rng = np.random.default_rng(50)
+    lengths = np.concatenate([rng.integers(1, 3000, 300), [60000, 9000, 2100]]).astype(np.int64)
+    res, offs = swinputs.make_database(lengths, rng)
+    q = swinputs.random_residues(40000, rng)
+    q2 = swinputs.random_residues(700, rng)
+    say("very long query and sequence")
+    want = _oracle(q, res, offs)
+    want2 = _oracle(q2, res, offs)
+    with sw.Database(res, offs) as db:
+        assert db.info()["n_long"] >= 3
+        got = db.search(q, B62, 10, 2)
+        gotb = db.search_batch([q, q2], B62, 10, 2)
+    assert (got == want).all()
+    assert (gotb[0] == want).all() and (gotb[1] == want2).all()
+
+
 def test_batch_and_async_match_single(sw):
     import torch
     res, offs = _ragged_db(7)
