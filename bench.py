@@ -35,17 +35,18 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection sources it was taken on:
 # bench reports null when their digest differs.
-TRAFFIC = {"bytes_per_launch": 1.7627e+10, "fetch_bytes": 49.70e9, "write_bytes": 302.84e9,
-           "launches": 20, "sources_sha256": "e35271ecc465a805748df8d9e9c6c82f86310be111f030dee7d7cfbe4eef24fe"}
+TRAFFIC = {"bytes_per_launch": 1.8747e+10, "fetch_bytes": 53.12e9, "write_bytes": 321.83e9,
+           "launches": 20, "sources_sha256": "bc926f7eb704a5c0d58e40686ca6a64d112316ac54fda39ad627463e1307dfd2"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
 # instruction x 2.4 GHz = 78.64 T half-ops/s
 PEAK_HALF_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # Packed binary16 instructions per cell pair of the recurrence on gfx950, as
-# half-ops per cell: 1 add + 3 subtract + 3 three-input max for the cell,
-# 1/2 three-input max for the running maximum (two rows per op), 1 byte
-# permute packing the two sequences' profile scores
-OPS_PER_CELL = 8.5
+# half-ops per cell: 1 fused multiply-add forming H_diag + S for both halves
+# (the profile dwords hold (S, 1) and (1, S)), 3 subtract and 3 three-input
+# max for the cell, 1/2 three-input max for the running maximum (two rows per
+# op): the algorithm's own work, no packing or address arithmetic
+OPS_PER_CELL = 7.5
 
 
 def sources_digest():

@@ -255,7 +255,8 @@ int sw_ctx_get_stats(sw_ctx* ctx, sw_stats* out);
  * position-major: dword res_off + (p/4)*128 + k holds positions p..p+3 of slot
  * k (byte p%4 = position p), padded with code SW_PAD_CODE up to the bin
  * length, a multiple of 4 and at least SW_MIN_BIN_LEN.  Each byte holds
- * 4 x the residue code (the code's byte offset in a 32-bit profile row).
+ * 8 x the residue code (the byte offset of the code's dword pair in a
+ * profile row pair).
  */
 #define SW_BIN_SEQS 128
 #define SW_PAD_CODE 24

@@ -21,12 +21,24 @@ struct Matrix {
   int8_t v[SW_ALPHA * SW_ALPHA];
 };
 
-// Inter-task profile: for each pair of query rows (2r, 2r+1), 26 dwords
-// (codes 0..23, the pad code 24, one spare); dword (r, c) = score of row 2r
-// against code c in bits 0..15, of row 2r+1 in bits 16..31, as binary16.
-// 13 dwords per query row.
-constexpr int kProfPairDwords = 26;
-constexpr int kProfRowDwords = 13;
+// Profile rows: 26 codes per query row (codes 0..23, the pad code 24, one
+// spare), one dword per row and code.  Rows are stored in pairs, code-major
+// within a pair: the dword of row 2r + t and code c sits at
+// r * kProfPairDwords + 2 * c + t, so one 64-bit LDS read at byte offset
+// 8 * c returns both rows of a pair (the residue bytes of the interleaved
+// store hold 8 x code).
+constexpr int kProfRowDwords = 26;
+constexpr int kProfPairDwords = 2 * kProfRowDwords;
+constexpr uint32_t kHalfOne = 0x3c00u;   // binary16 1.0
+// Inter-task profile, strip-major for strips of R rows: strip s holds two
+// tables of R rows in the row-pair layout, the low table with dwords
+// (S(a_i, c), 1) and the high table with dwords (1, S(a_i, c)), binary16
+// (2 * R * kProfRowDwords dwords per strip).  A lane whose two sequences
+// have residues x and y reads (S(a_i, x), 1) from the low table and
+// (1, S(a_i, y)) from the high one; their packed product is (S(a_i, x),
+// S(a_i, y)), so one packed fused multiply-add forms H_diag + S for both
+// sequences.
+__host__ __device__ constexpr int prof_strip_dwords(int R) { return 2 * R * kProfRowDwords; }
 // Score given to padding (pad code, and query rows past the end).  Any value
 // <= 0 keeps padded cells from raising a maximum.
 constexpr int kPadScore = -64;
@@ -54,7 +66,7 @@ struct InterArgs {
   const BinDesc* bins;
   int32_t bin_begin;          // first bin of this launch
   int32_t n_strips;           // query strips of R rows
-  const uint32_t* prof;       // [n_strips * R][13] dwords
+  const uint32_t* prof;       // n_strips * prof_strip_dwords(R) dwords
   uint32_t go2, ge2;          // gap penalties (binary16, capped at 2048) in both halves
   uint4* rb;                  // boundary-row buffers of all bins
   const int32_t* slot_seq;
@@ -108,11 +120,13 @@ struct IntraPairArgs {
 };
 
 // Batched inter-task kernel: the two 16-bit halves of a lane hold two
-// queries (a pair) against one database sequence.
-constexpr int kBatchRowDwords = 26;   // dword (i, c) = (S(a_i, c), S(b_i, c))
+// queries (a pair) against one database sequence.  The pair's profile has
+// the inter-task layout (rows in pairs, code-major within a pair) with the
+// dword of row i and code c holding (S(a_i, c), S(b_i, c)).
+constexpr int kBatchRowDwords = kProfRowDwords;
 
 struct PairDesc {
-  int64_t prof_off;           // dword offset of the pair's [rows][26] profile
+  int64_t prof_off;           // dword offset of the pair's [rows / 2][26][2] profile
   int32_t n_strips;           // strips of R rows covering the longer query
   int32_t qa, qb;             // query indices (qb < 0: high half unused)
   int32_t pad_;
@@ -139,7 +153,7 @@ struct BatchArgs {
 
 // Kernel launchers (return hipSuccess or the launch error).
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
-                          int m_pad, int8_t* prof2, uint32_t* prof3, int m_pad2,
+                          int m_pad, int R, int8_t* prof2, uint32_t* prof3, int m_pad2,
                           int32_t* flag_count, hipStream_t s);
 hipError_t launch_fill(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_t s);

@@ -6,9 +6,10 @@
 // register hold the two queries of a pair, scored against the same database
 // sequence, so each lane owns one sequence and a wave 64.  The profile of a
 // pair stores, for query row i and residue code c, the dword
-// (S(a_i, c), S(b_i, c)): one 32-bit LDS read per row returns both halves'
-// scores with no packing op, and all lanes read the same 26-dword row, so the
-// reads never conflict on banks.  The cell arithmetic, the R-row strips, the
+// (S(a_i, c), S(b_i, c)), rows in pairs and code-major within a pair: one
+// 64-bit LDS read per row pair returns both halves' scores for two rows with
+// no packing op (all lanes read the same 208-byte row pair; codes 16 apart
+// share a pair of banks).  The cell arithmetic, the R-row strips, the
 // W-wave strip pipeline and the boundary-row handling are those of the
 // single-query inter-task kernel (k_inter.hip).
 //
@@ -28,7 +29,8 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
   constexpr int D = 2;   // superstep skew between consecutive waves
   constexpr int kSlot = R * kBatchRowDwords;
   constexpr int kStage = (kSlot + 63) / 64;
-  __shared__ uint32_t lprof[W][2][kSlot];
+  static_assert(kStage <= SW_MIN_BIN_LEN / 4, "the staging needs kStage chunks per strip");
+  __shared__ __attribute__((aligned(16))) uint32_t lprof[W][2][kSlot];
   __shared__ uint32_t lbest[W][64];
   __shared__ int litem;
 
@@ -105,33 +107,32 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
         const uint32_t up_f[4] = {b_n.y, b_n.w, b_n2.y, b_n2.w};
         if (c + 1 < C) fetch(s, c + 1);
         else if (more) fetch(s + Wu, 0);
-        const bool stage = more && c == C - 1;
-        uint32_t st[kStage];
-        if (stage) {
-          const uint32_t* src = prof + (size_t)(s + Wu) * kSlot;
-#pragma unroll
-          for (int x = 0; x < kStage; ++x)
-            if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
-        }
+        // next strip's profile, piece x = c - (C - kStage) of kStage, one
+        // dword per lane: the global load now, the LDS store after the compute
+        const int x_st = c - (C - kStage);
+        const bool stage = more && x_st >= 0 && x_st * 64 + lane < kSlot;
+        uint32_t st = 0;
+        if (stage) st = prof[(size_t)(s + Wu) * kSlot + x_st * 64 + lane];
         uint32_t out_h[4], out_f[4];
-        // residue bytes hold 4 x code, the code's byte offset in a row
-        sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
-                       [&](int jj, uint32_t (&p)[R]) {
-          const uint32_t* pc = reinterpret_cast<const uint32_t*>(
+        // residue bytes hold 8 x code, the byte offset of the code's dword
+        // pair in a row pair: one 64-bit LDS read gives two rows
+        sweep_chunk<R, false>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                              [&](int jj, uint32_t (&p)[R], uint32_t (&)[R]) {
+          const uint2* pc = reinterpret_cast<const uint2*>(
               reinterpret_cast<const char*>(slot) + ((rr >> (8 * jj)) & 0xffu));
 #pragma unroll
-          for (int k = 0; k < R; ++k) p[k] = pc[k * kBatchRowDwords];
+          for (int k2 = 0; k2 < R / 2; ++k2) {
+            const uint2 A = pc[k2 * kBatchRowDwords];
+            p[2 * k2] = A.x;
+            p[2 * k2 + 1] = A.y;
+          }
         });
         if (s < S - 1) {
           uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
           p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
           p[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
         }
-        if (stage) {
-#pragma unroll
-          for (int x = 0; x < kStage; ++x)
-            if (x * 64 + lane < kSlot) lprof[w][(q + 1) & 1][x * 64 + lane] = st[x];
-        }
+        if (stage) lprof[w][(q + 1) & 1][x_st * 64 + lane] = st;
         __syncthreads();
       }
     }

@@ -31,12 +31,19 @@
 // Splitting one bin's strips over W waves divides its latency by W, which
 // keeps the longest bins from trailing the rest of the grid.
 //
-// The query profile rows of the current strip are staged in LDS as row pairs:
-// dword (r, c) holds the scores of query rows 2r and 2r+1 against residue
-// code c (26 codes: 24 residues, pad, spare).  All lanes read the same row
-// pair at once, so the addresses fall in 26 consecutive dwords: no bank
-// conflicts.  One read per row pair and half (lo/hi sequence) yields two
-// rows; one byte permute per row packs the lo and hi sequences' scores.
+// The query profile rows of the current strip are staged in LDS as two
+// tables (internal.h, prof_strip_dwords): the low table holds (S(a_i, c), 1)
+// and the high table (1, S(a_i, c)) as binary16, for 26 codes (24 residues,
+// pad, spare), rows in pairs and code-major within a pair.  Per row pair a
+// lane reads one 64-bit entry for its low sequence's residue x from the low
+// table and one for its high sequence's residue y from the high table; the
+// packed product (S(a_i, x), 1) * (1, S(a_i, y)) is (S(a_i, x), S(a_i, y)),
+// so one packed fused multiply-add per cell forms H_diag + S for both
+// sequences, with no byte permute.  All lanes read the same row pair, so the
+// addresses fall in one 208-byte row pair of each table (two codes share a
+// pair of 32-bit banks when they are 16 apart).  The next strip's rows are
+// copied in during the current strip's last chunks, one or two dwords per
+// lane per chunk, so the copy holds few registers.
 #include "internal.h"
 #include "packed16.h"
 
@@ -46,9 +53,13 @@ namespace {
 template <int R, int W>
 __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   constexpr int D = 2;   // superstep skew between consecutive waves
-  constexpr int kSlot = R * kProfRowDwords;
-  constexpr int kStage = (kSlot + 63) / 64;
-  __shared__ uint32_t lprof[W][2][kSlot];
+  constexpr int kSlot = prof_strip_dwords(R);
+  constexpr int kHighBytes = R * kProfRowDwords * 4;   // the high table's offset
+  constexpr int kStage = (kSlot + 63) / 64;            // dwords per lane per strip
+  constexpr int kPer = (kStage + 15) / 16;             // staged per chunk
+  constexpr int kStageChunks = (kStage + kPer - 1) / kPer;
+  static_assert(kStageChunks <= SW_MIN_BIN_LEN / 4, "the staging needs kStageChunks chunks");
+  __shared__ __attribute__((aligned(16))) uint32_t lprof[W][2][kSlot];
   __shared__ uint32_t lbest[W][64];
 
   const int lane = threadIdx.x & 63;
@@ -77,19 +88,18 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   uint4* __restrict__ rbb = a.rb + bin.rb_off;
   const uint32_t go = a.go2, ge = a.ge2;
 
-  // inputs of the next chunk, fetched one superstep ahead
+  // inputs of the next chunk, fetched one superstep ahead.  The first strip
+  // reads the boundary buffer too: every bin's buffer holds zeros between
+  // searches (zeroed when allocated, and the last strip of every search
+  // writes zeros in place of its bottom row), so every chunk issues the
+  // same memory operations and the compiler can count them exactly.
   uint2 rr_n = make_uint2(0, 0);
   uint4 b0_n = make_uint4(0, 0, 0, 0), b1_n = make_uint4(0, 0, 0, 0);
-  auto fetch = [&](int s, int c) {
+  auto fetch = [&](int c) {
     rr_n = rbin[c * 64 + lane];
-    if (s > 0) {
-      const uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
-      b0_n = p[0];
-      b1_n = p[1];
-    } else {
-      b0_n = make_uint4(0, 0, 0, 0);
-      b1_n = make_uint4(0, 0, 0, 0);
-    }
+    const uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
+    b0_n = p[0];
+    b1_n = p[1];
   };
 
   uint32_t H[R], E[R];
@@ -104,9 +114,9 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   // Every wave passes exactly T_total barriers: its lead-in (all of T_total
   // for an idle wave), my_rounds * C supersteps of work, then the tail.
   const int lead = min(D * w, T_total);
-  if (w == 0 && my_rounds > 0) fetch(0, 0);
+  if (w == 0 && my_rounds > 0) fetch(0);
   for (int T = 0; T < lead; ++T) {
-    if (T == D * w - 1 && my_rounds > 0) fetch(w, 0);
+    if (T == D * w - 1 && my_rounds > 0) fetch(0);
     __syncthreads();
   }
   for (int q = 0; q < my_rounds; ++q) {
@@ -120,44 +130,56 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
       const uint2 rr = rr_n;
       const uint32_t up_h[4] = {b0_n.x, b0_n.z, b1_n.x, b1_n.z};
       const uint32_t up_f[4] = {b0_n.y, b0_n.w, b1_n.y, b1_n.w};
-      if (c + 1 < C) fetch(s, c + 1);
-      else if (more) fetch(s + Wu, 0);
-      // next strip's profile: global loads now, LDS stores after the compute
-      const bool stage = more && c == C - 1;
-      uint32_t st[kStage];
-      if (stage) {
-        const uint32_t* src = a.prof + (size_t)(s + Wu) * kSlot;
+      // the next chunk, or the first chunk of the next strip (after the last
+      // strip a harmless reload of chunk 0)
+      fetch(c + 1 < C ? c + 1 : 0);
+      // next strip's profile, pieces kPer * x .. kPer * x + kPer - 1 of
+      // kStage with x = c - (C - kStageChunks): the global loads now (always
+      // issued, from this strip's own profile when there is nothing to
+      // stage), the LDS stores after the compute
+      const int x_st = c - (C - kStageChunks);
+      const bool stage = more && x_st >= 0;
+      const uint32_t* st_src = a.prof + (size_t)(stage ? s + Wu : s) * kSlot;
+      uint32_t st[kPer];
 #pragma unroll
-        for (int x = 0; x < kStage; ++x)
-          if (x * 64 + lane < kSlot) st[x] = src[x * 64 + lane];
-      }
+      for (int y = 0; y < kPer; ++y)
+        st[y] = st_src[min((kPer * max(x_st, 0) + y) * 64 + lane, kSlot - 1)];
+      __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the compute
       uint32_t out_h[4], out_f[4];
-      // one 32-bit LDS read per row pair and sequence gives two rows'
-      // scores; a byte permute per row packs the lo and hi sequences'.  The
-      // residue bytes hold 4 x code, the code's byte offset in a row pair.
-      sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
-                     [&](int jj, uint32_t (&p)[R]) {
-        const uint32_t* plo = reinterpret_cast<const uint32_t*>(
+      // one 64-bit LDS read per row pair and sequence gives both rows'
+      // dwords, (S, 1) from the low table for the low half's residue and
+      // (1, S) from the high table for the high half's (two reads per
+      // ds_read2_b64); the residue bytes hold 8 x code, the byte offset of
+      // the code's dword pair in a row pair.
+      sweep_chunk<R, true>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                           [&](int jj, uint32_t (&p)[R], uint32_t (&p2)[R]) {
+        const uint2* plo = reinterpret_cast<const uint2*>(
             reinterpret_cast<const char*>(slot) + ((rr.x >> (8 * jj)) & 0xffu));
-        const uint32_t* phi = reinterpret_cast<const uint32_t*>(
-            reinterpret_cast<const char*>(slot) + ((rr.y >> (8 * jj)) & 0xffu));
+        const uint2* phi = reinterpret_cast<const uint2*>(
+            reinterpret_cast<const char*>(slot) + kHighBytes + ((rr.y >> (8 * jj)) & 0xffu));
 #pragma unroll
         for (int k2 = 0; k2 < R / 2; ++k2) {
-          const uint32_t A = plo[k2 * kProfPairDwords], B = phi[k2 * kProfPairDwords];
-          // v_perm_b32: bytes {A0, A1, B0, B1} and {A2, A3, B2, B3}
-          p[2 * k2] = __builtin_amdgcn_perm(B, A, 0x05040100u);
-          p[2 * k2 + 1] = __builtin_amdgcn_perm(B, A, 0x07060302u);
+          const uint2 A = plo[k2 * kProfRowDwords], B = phi[k2 * kProfRowDwords];
+          p[2 * k2] = A.x;
+          p[2 * k2 + 1] = A.y;
+          p2[2 * k2] = B.x;
+          p2[2 * k2 + 1] = B.y;
         }
       });
+      uint4* pb = rbb + (size_t)(c * 64 + lane) * 2;
       if (s < S - 1) {
-        uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
-        p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
-        p[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+        pb[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
+        pb[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+      } else {   // the last strip leaves the buffer zeroed for the next search
+        pb[0] = make_uint4(0, 0, 0, 0);
+        pb[1] = make_uint4(0, 0, 0, 0);
       }
       if (stage) {
 #pragma unroll
-        for (int x = 0; x < kStage; ++x)
-          if (x * 64 + lane < kSlot) lprof[w][(q + 1) & 1][x * 64 + lane] = st[x];
+        for (int y = 0; y < kPer; ++y) {
+          const int o = (kPer * x_st + y) * 64 + lane;
+          if (o < kSlot) lprof[w][(q + 1) & 1][o] = st[y];
+        }
       }
       __syncthreads();
     }

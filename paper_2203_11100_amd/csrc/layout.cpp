@@ -126,7 +126,7 @@ void fill_layout(const uint8_t* residues, const int64_t* offsets, const Plan& pl
         uint32_t w = 0;
         for (int x = 0; x < 4; ++x) {
           const uint32_t c = (p + x < sl) ? s[p + x] : (uint32_t)SW_PAD_CODE;
-          w |= (c << 2) << (8 * x);   // 4 x code: byte offset in a profile row
+          w |= (c << 3) << (8 * x);   // 8 x code: byte offset in a profile row pair
         }
         packed[res_off + (p / 4) * SW_BIN_SEQS + k] = w;
       }

@@ -31,6 +31,12 @@ __device__ __forceinline__ uint32_t as_u32(h16x2 a) { return __builtin_bit_cast(
 // per half: a + b, a - b (v_pk_add_f16)
 __device__ __forceinline__ uint32_t hadd(uint32_t a, uint32_t b) { return as_u32(as_h2(a) + as_h2(b)); }
 __device__ __forceinline__ uint32_t hsub(uint32_t a, uint32_t b) { return as_u32(as_h2(a) - as_h2(b)); }
+// per half: a * b + c (v_pk_fma_f16).  With a = (S_x, 1) and b = (1, S_y)
+// it is c + (S_x, S_y): the products by 1 are exact and the sum rounds
+// once, exactly as the add would.
+__device__ __forceinline__ uint32_t hfma(uint32_t a, uint32_t b, uint32_t c) {
+  return as_u32(__builtin_elementwise_fma(as_h2(a), as_h2(b), as_h2(c)));
+}
 // per half: max(a, b) and max(a, b, c) (v_pk_maximum3_f16)
 __device__ __forceinline__ uint32_t hmax2(uint32_t a, uint32_t b) {
   return as_u32(__builtin_elementwise_maximum(as_h2(a), as_h2(b)));
@@ -49,17 +55,25 @@ __device__ __forceinline__ int half_score(uint32_t v, int half, int limit) {
 
 // One cell of Gotoh's recurrence on both halves, with E and F kept as
 // max(E, 0) and max(F, 0) (then H = max(H_diag + S, E, F) needs no 0):
-//   h = max(hd + p, E, F);  t = h - o;  E = max(E - e, t, 0);  F = max(F - e, t, 0)
-// hd enters as H(i-1, j-1) and leaves as H(i, j-1) (the next row's
-// diagonal); H enters as H(i, j-1) and leaves as H(i, j).  Returns h.
-__device__ __forceinline__ uint32_t cell(uint32_t& hd, uint32_t& H, uint32_t& E, uint32_t& F,
-                                         uint32_t p, uint32_t go, uint32_t ge) {
-  const uint32_t h = hmax3(hadd(hd, p), E, F);
-  hd = H;
-  H = h;
+//   h = max(d, E, F);  t = h - o;  E = max(E - e, t, 0);  F = max(F - e, t, 0)
+// where d = H(i-1, j-1) + S(a_i, b_j).  Returns h.
+__device__ __forceinline__ uint32_t cell_from_diag(uint32_t d, uint32_t& E, uint32_t& F,
+                                                   uint32_t go, uint32_t ge) {
+  const uint32_t h = hmax3(d, E, F);
   const uint32_t t = hsub(h, go);
   E = hmax3(hsub(E, ge), t, 0u);
   F = hmax3(hsub(F, ge), t, 0u);
+  return h;
+}
+
+// The cell with packed scores p: hd enters as H(i-1, j-1) and leaves as
+// H(i, j-1) (the next row's diagonal); H enters as H(i, j-1) and leaves as
+// H(i, j).  Returns h.
+__device__ __forceinline__ uint32_t cell(uint32_t& hd, uint32_t& H, uint32_t& E, uint32_t& F,
+                                         uint32_t p, uint32_t go, uint32_t ge) {
+  const uint32_t h = cell_from_diag(hadd(hd, p), E, F, go, ge);
+  hd = H;
+  H = h;
   return h;
 }
 
@@ -67,12 +81,16 @@ __device__ __forceinline__ uint32_t cell(uint32_t& hd, uint32_t& H, uint32_t& E,
 // running maximum takes two rows per 3-input max.  (Sweeping bands of two or
 // four columns along anti-diagonals, which removes the wait states between
 // dependent packed ops, measured 5 % and 7 % slower on gfx950.)
-//   prof(jj, p)  fills p[0..R-1] with the packed scores of column jj
+//   prof(jj, p, p2)  fills, for column jj, p[0..R-1] with the packed scores
+//                (kSplit false), or p with the (S, 1) dwords of the low half's
+//                residue and p2 with the (1, S) dwords of the high half's
+//                (kSplit true: one fused multiply-add per cell forms
+//                H_diag + S, see hfma)
 //   hdiag        H of the row above the strip at the column before the chunk;
 //                leaves as that of the chunk's last column
 //   up_h, up_f   H and F of the row above the strip, per column
 //   out_h, out_f H and F of the strip's bottom row, per column
-template <int R, class Prof>
+template <int R, bool kSplit, class Prof>
 __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], uint32_t& hdiag,
                                             const uint32_t (&up_h)[4], const uint32_t (&up_f)[4],
                                             uint32_t (&out_h)[4], uint32_t (&out_f)[4],
@@ -80,15 +98,18 @@ __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], 
   static_assert(R % 2 == 0, "rows are taken in pairs for the maximum");
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
-    uint32_t p[R];
-    prof(jj, p);
+    uint32_t p[R], p2[R];
+    prof(jj, p, p2);
     uint32_t hd = hdiag;
     hdiag = up_h[jj];
     uint32_t F = up_f[jj];
     uint32_t hprev = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const uint32_t h = cell(hd, H[k], E[k], F, p[k], go, ge);
+      const uint32_t d = kSplit ? hfma(p[k], p2[k], hd) : hadd(hd, p[k]);
+      const uint32_t h = cell_from_diag(d, E[k], F, go, ge);
+      hd = H[k];
+      H[k] = h;
       if (k & 1) best = hmax3(best, hprev, h);
       else hprev = h;
     }

@@ -268,6 +268,11 @@ int init_searcher(Searcher* S, DbData* d) {
            (size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)))) !=
           hipSuccess)
     return fail(SW_ENOMEM, std::string("search scratch: ") + hipGetErrorString(e));
+  // the inter-task kernel's first strip reads zeros from the boundary rows;
+  // every search leaves them zeroed again
+  if ((e = hipMemset(S->rb.p, 0, (size_t)std::max<int64_t>(P.boundary_uint4, 1) * sizeof(uint4))) !=
+      hipSuccess)
+    return hip_fail(e, "boundary-row clear");
   if ((e = hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&S->aux_stream, hipStreamNonBlocking)) != hipSuccess)
     return hip_fail(e, "stream creation");
@@ -466,7 +471,7 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   const int rows2 = 64 * std::max(RR, RRr);
   const int m_pad2 = (m + rows2 - 1) / rows2 * rows2;
 
-  if ((e = db->prof.reserve((size_t)m_pad * kProfRowDwords)) != hipSuccess)
+  if ((e = db->prof.reserve((size_t)n_strips * prof_strip_dwords(R))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
   if ((e = db->prof2.reserve((size_t)kIntraCodes * m_pad2)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
@@ -474,7 +479,7 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
 
   const int t_total = time_begin(db, kTimeTotal, s);
-  if ((e = launch_profile(d_query, m, mat, db->prof.p, m_pad, db->prof2.p,
+  if ((e = launch_profile(d_query, m, mat, db->prof.p, m_pad, R, db->prof2.p,
                           n_long > 0 ? db->prof3.p : nullptr, m_pad2, db->flags.p, s)) !=
       hipSuccess)
     return hip_fail(e, "profile kernel");

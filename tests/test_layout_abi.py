@@ -29,8 +29,8 @@ def _unpack(p, offsets):
         for k in range(sw.SW_BIN_SEQS):
             words = packed[res_off + k: res_off + (blen // 4) * sw.SW_BIN_SEQS: sw.SW_BIN_SEQS]
             raw = np.ascontiguousarray(words).view(np.uint8).reshape(-1)  # byte x = position 4q+x
-            assert (raw % 4 == 0).all()      # bytes hold 4 x code
-            codes = raw // 4
+            assert (raw % 8 == 0).all()      # bytes hold 8 x code
+            codes = raw // 8
             sid = p["slot_seq"][slot0 + k]
             if sid < 0:
                 assert (codes == sw.SW_PAD_CODE).all()
