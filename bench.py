@@ -35,8 +35,8 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection sources it was taken on:
 # bench reports null when their digest differs.
-TRAFFIC = {"bytes_per_launch": 1.8747e+10, "fetch_bytes": 53.12e9, "write_bytes": 321.83e9,
-           "launches": 20, "sources_sha256": "bc926f7eb704a5c0d58e40686ca6a64d112316ac54fda39ad627463e1307dfd2"}
+TRAFFIC = {"bytes_per_launch": 1.8611e+10, "fetch_bytes": 53.50e9, "write_bytes": 318.72e9,
+           "launches": 20, "sources_sha256": "3d29968bc5c73a917e8f8f0e4bc61a42fd316b66ce8787c88a21de5b32d6b13f"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
 # instruction x 2.4 GHz = 78.64 T half-ops/s

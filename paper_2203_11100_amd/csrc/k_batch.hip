@@ -115,9 +115,11 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
         if (stage) st = prof[(size_t)(s + Wu) * kSlot + x_st * 64 + lane];
         uint32_t out_h[4], out_f[4];
         // residue bytes hold 8 x code, the byte offset of the code's dword
-        // pair in a row pair: one 64-bit LDS read gives two rows
-        sweep_chunk<R, false>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
-                              [&](int jj, uint32_t (&p)[R], uint32_t (&)[R]) {
+        // pair in a row pair: one 64-bit LDS read gives two rows (reading a
+        // column ahead, as the single-query kernel does, measured 2 % slower
+        // here: one table, half the reads to hide)
+        sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                       [&](int jj, uint32_t (&p)[R]) {
           const uint2* pc = reinterpret_cast<const uint2*>(
               reinterpret_cast<const char*>(slot) + ((rr >> (8 * jj)) & 0xffu));
 #pragma unroll

@@ -119,6 +119,19 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
     if (T == D * w - 1 && my_rounds > 0) fetch(0);
     __syncthreads();
   }
+  // one 64-bit LDS read per row pair and sequence gives both rows' dwords,
+  // (S, 1) from the low table for the low half's residue and (1, S) from the
+  // high table for the high half's (two reads per ds_read2_b64 where they
+  // pair); the residue bytes hold 8 x code, the byte offset of the code's
+  // dword pair in a row pair
+  auto read_pair = [&](const uint32_t* sl, uint2 res, int jj, int k2, uint2& A, uint2& B) {
+    const uint2* plo = reinterpret_cast<const uint2*>(
+        reinterpret_cast<const char*>(sl) + ((res.x >> (8 * jj)) & 0xffu));
+    const uint2* phi = reinterpret_cast<const uint2*>(
+        reinterpret_cast<const char*>(sl) + kHighBytes + ((res.y >> (8 * jj)) & 0xffu));
+    A = plo[k2 * kProfRowDwords];
+    B = phi[k2 * kProfRowDwords];
+  };
   for (int q = 0; q < my_rounds; ++q) {
     const int s = q * Wu + w;
 #pragma unroll
@@ -146,33 +159,17 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
         st[y] = st_src[min((kPer * max(x_st, 0) + y) * 64 + lane, kSlot - 1)];
       __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the compute
       uint32_t out_h[4], out_f[4];
-      // one 64-bit LDS read per row pair and sequence gives both rows'
-      // dwords, (S, 1) from the low table for the low half's residue and
-      // (1, S) from the high table for the high half's (two reads per
-      // ds_read2_b64); the residue bytes hold 8 x code, the byte offset of
-      // the code's dword pair in a row pair.
-      sweep_chunk<R, true>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
-                           [&](int jj, uint32_t (&p)[R], uint32_t (&p2)[R]) {
-        const uint2* plo = reinterpret_cast<const uint2*>(
-            reinterpret_cast<const char*>(slot) + ((rr.x >> (8 * jj)) & 0xffu));
-        const uint2* phi = reinterpret_cast<const uint2*>(
-            reinterpret_cast<const char*>(slot) + kHighBytes + ((rr.y >> (8 * jj)) & 0xffu));
-#pragma unroll
-        for (int k2 = 0; k2 < R / 2; ++k2) {
-          const uint2 A = plo[k2 * kProfRowDwords], B = phi[k2 * kProfRowDwords];
-          p[2 * k2] = A.x;
-          p[2 * k2 + 1] = A.y;
-          p2[2 * k2] = B.x;
-          p2[2 * k2 + 1] = B.y;
-        }
+      sweep_chunk_ahead<R, true>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+                                 [&](int jj, int k2, uint2& A, uint2& B) {
+        read_pair(slot, rr, jj, k2, A, B);
       });
-      uint4* pb = rbb + (size_t)(c * 64 + lane) * 2;
+      uint4* pbd = rbb + (size_t)(c * 64 + lane) * 2;
       if (s < S - 1) {
-        pb[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
-        pb[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
+        pbd[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
+        pbd[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
       } else {   // the last strip leaves the buffer zeroed for the next search
-        pb[0] = make_uint4(0, 0, 0, 0);
-        pb[1] = make_uint4(0, 0, 0, 0);
+        pbd[0] = make_uint4(0, 0, 0, 0);
+        pbd[1] = make_uint4(0, 0, 0, 0);
       }
       if (stage) {
 #pragma unroll

@@ -81,16 +81,12 @@ __device__ __forceinline__ uint32_t cell(uint32_t& hd, uint32_t& H, uint32_t& E,
 // running maximum takes two rows per 3-input max.  (Sweeping bands of two or
 // four columns along anti-diagonals, which removes the wait states between
 // dependent packed ops, measured 5 % and 7 % slower on gfx950.)
-//   prof(jj, p, p2)  fills, for column jj, p[0..R-1] with the packed scores
-//                (kSplit false), or p with the (S, 1) dwords of the low half's
-//                residue and p2 with the (1, S) dwords of the high half's
-//                (kSplit true: one fused multiply-add per cell forms
-//                H_diag + S, see hfma)
+//   prof(jj, p)  fills p[0..R-1] with the packed scores of column jj
 //   hdiag        H of the row above the strip at the column before the chunk;
 //                leaves as that of the chunk's last column
 //   up_h, up_f   H and F of the row above the strip, per column
 //   out_h, out_f H and F of the strip's bottom row, per column
-template <int R, bool kSplit, class Prof>
+template <int R, class Prof>
 __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], uint32_t& hdiag,
                                             const uint32_t (&up_h)[4], const uint32_t (&up_f)[4],
                                             uint32_t (&out_h)[4], uint32_t (&out_f)[4],
@@ -98,20 +94,74 @@ __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], 
   static_assert(R % 2 == 0, "rows are taken in pairs for the maximum");
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
-    uint32_t p[R], p2[R];
-    prof(jj, p, p2);
+    uint32_t p[R];
+    prof(jj, p);
     uint32_t hd = hdiag;
     hdiag = up_h[jj];
     uint32_t F = up_f[jj];
     uint32_t hprev = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-      const uint32_t d = kSplit ? hfma(p[k], p2[k], hd) : hadd(hd, p[k]);
-      const uint32_t h = cell_from_diag(d, E[k], F, go, ge);
+      const uint32_t h = cell_from_diag(hadd(hd, p[k]), E[k], F, go, ge);
       hd = H[k];
       H[k] = h;
       if (k & 1) best = hmax3(best, hprev, h);
       else hprev = h;
+    }
+    out_h[jj] = H[R - 1];
+    out_f[jj] = F;
+  }
+}
+
+// sweep_chunk with the profile reads issued one column ahead: while row pair
+// k2 of column jj is computed, row pair k2 of column jj + 1 is read, so the
+// reads' latency hides behind a column of arithmetic (the chunk's first
+// column is read at its start).  The registers held stay those of one
+// column: a row pair's old values die as its new ones are read.  (Reading
+// the next chunk's first column during the last column as well keeps those
+// registers live across the chunk boundary and spills.)
+//   prof_pair(jj, k2, a, b)  reads row pair k2 of column jj: with kSplit,
+//                a = the low table's two (S, 1) dwords and b = the high
+//                table's two (1, S) dwords, one fused multiply-add per cell
+//                forming H_diag + S (see hfma); without, a = the two rows'
+//                packed scores, added to H_diag (b unused)
+template <int R, bool kSplit, class ProfPair>
+__device__ __forceinline__ void sweep_chunk_ahead(uint32_t (&H)[R], uint32_t (&E)[R],
+                                                  uint32_t& hdiag, const uint32_t (&up_h)[4],
+                                                  const uint32_t (&up_f)[4], uint32_t (&out_h)[4],
+                                                  uint32_t (&out_f)[4], uint32_t& best,
+                                                  uint32_t go, uint32_t ge, ProfPair prof_pair) {
+  static_assert(R % 2 == 0, "rows are taken in pairs");
+  // VALU and SALU may cross the scheduling barriers; LDS reads may not
+  constexpr int kMayCross = 0x0002 | 0x0004;
+  uint2 a[R / 2], b[R / 2];
+#pragma unroll
+  for (int k2 = 0; k2 < R / 2; ++k2) prof_pair(0, k2, a[k2], b[k2]);
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+    uint32_t hd = hdiag;
+    hdiag = up_h[jj];
+    uint32_t F = up_f[jj];
+#pragma unroll
+    for (int k2 = 0; k2 < R / 2; ++k2) {
+      // an empty asm taking the F that enters the row pair keeps the first
+      // use of its scores (read a column earlier) where the F chain reaches it
+      if (kSplit) asm volatile("" : "+v"(a[k2]), "+v"(b[k2]) : "v"(F));
+      else asm volatile("" : "+v"(a[k2]) : "v"(F));
+      const uint2 ca = a[k2], cb = b[k2];
+      if (jj < 3) {
+        prof_pair(jj + 1, k2, a[k2], b[k2]);
+        __builtin_amdgcn_sched_barrier(kMayCross);
+      }
+      const uint32_t d0 = kSplit ? hfma(ca.x, cb.x, hd) : hadd(hd, ca.x);
+      const uint32_t h0 = cell_from_diag(d0, E[2 * k2], F, go, ge);
+      hd = H[2 * k2];
+      H[2 * k2] = h0;
+      const uint32_t d1 = kSplit ? hfma(ca.y, cb.y, hd) : hadd(hd, ca.y);
+      const uint32_t h1 = cell_from_diag(d1, E[2 * k2 + 1], F, go, ge);
+      hd = H[2 * k2 + 1];
+      H[2 * k2 + 1] = h1;
+      best = hmax3(best, h0, h1);
     }
     out_h[jj] = H[R - 1];
     out_f[jj] = F;

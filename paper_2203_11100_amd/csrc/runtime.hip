@@ -306,24 +306,26 @@ int tune_bucket(int m) {
 }
 
 // Default schedule of the inter-task kernels: 16-row strips and 12 waves per
-// bin (three waves per SIMD at 136 VGPRs; measured faster than 32 x 8 for
+// bin (three waves per SIMD at 138 VGPRs; measured faster than 32 x 8 for
 // every query length of the plain workload and for the batched one).
 constexpr int kDefaultRows = 16, kDefaultWaves = 12;
 
 // The fitted schedules of the single-query inter-task kernel: strip height
-// R and waves W with the fraction of the packed VALU peak each sustains per
-// strip slot, measured on the plain workload's three longest queries (where
-// every schedule fills its rounds): 12 waves (3 per SIMD) with 12..20 rows,
-// 16 waves (4 per SIMD, <= 128 VGPRs) with 12 or 14 rows.
+// R and waves W with a relative efficiency per strip slot, the median over
+// the plain workload's queries of 700+ rows of GCUPS x padded rows / rows
+// (scaled to 0.868 for 14 x 16): 12 waves (3 per SIMD) with 12..20 rows, 16
+// waves (4 per SIMD, <= 128 VGPRs) with 12 or 14 rows.
 struct Sched {
   int R, W;
   double eff;
 };
-constexpr Sched kScheds[] = {{20, 12, 0.849}, {18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
-                             {12, 12, 0.781}, {14, 16, 0.868}, {12, 16, 0.832}};
+constexpr Sched kScheds[] = {{20, 12, 0.836}, {18, 12, 0.842}, {16, 12, 0.834}, {14, 12, 0.827},
+                             {12, 12, 0.788}, {14, 16, 0.868}, {12, 16, 0.825}};
 
 // The batched kernel's fitted schedules (the 20 x 12 and 14 x 16 forms
-// spill registers there); efficiencies taken from the single-query table.
+// spill registers there); efficiencies measured the same way on the
+// single-query kernel when it, like the batched kernel, read each column's
+// profile at the column's start.
 constexpr Sched kBatchScheds[] = {{18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
                                   {12, 12, 0.781}, {12, 16, 0.832}};
 

@@ -80,8 +80,8 @@ def test_strip_and_wave_options(sw, rows, waves):
 
 
 # (rows, waves, efficiency per strip slot) of the library's fitted schedules
-_SCHEDS = [(20, 12, 0.849), (18, 12, 0.851), (16, 12, 0.830), (14, 12, 0.812),
-           (12, 12, 0.781), (14, 16, 0.868), (12, 16, 0.832)]
+_SCHEDS = [(20, 12, 0.836), (18, 12, 0.842), (16, 12, 0.834), (14, 12, 0.827),
+           (12, 12, 0.788), (14, 16, 0.868), (12, 16, 0.825)]
 
 
 def _fit_schedule(m):
