@@ -79,6 +79,26 @@ def test_strip_and_wave_options(sw, rows, waves):
     assert (got == _oracle(q, res, offs)).all()
 
 
+def test_consecutive_searches_change_schedule(sw):
+    """Searches in a row on one database, each with another schedule and
+    query length (one strip, several rounds, a single-wave form, an empty
+    query): the first strip of every search reads the boundary rows the
+    previous search left, which must be zeros whatever its schedule."""
+    res, offs = _ragged_db(7)
+    rng = np.random.default_rng(70)
+    plan = [(333, 0, 0), (5, 12, 16), (700, 20, 12), (0, 0, 0), (40, 14, 16),
+            (150, 16, 1), (1, 0, 0), (900, 32, 8), (211, 18, 12), (333, 0, 0)]
+    say("consecutive searches, %d schedules" % len(plan))
+    with sw.Database(res, offs) as db:
+        for m, rows, waves in plan:
+            q = swinputs.random_residues(m, rng)
+            db.set_option(sw.SW_OPT_ROWS, rows)
+            db.set_option(sw.SW_OPT_WAVES, waves)
+            got = db.search(q, B62, 10, 2)
+            want = _oracle(q, res, offs) if m else np.zeros(len(offs) - 1, np.int32)
+            assert (got == want).all(), (m, rows, waves)
+
+
 # (rows, waves, efficiency per strip slot) of the library's fitted schedules
 _SCHEDS = [(20, 12, 0.836), (18, 12, 0.842), (16, 12, 0.834), (14, 12, 0.827),
            (12, 12, 0.788), (14, 16, 0.868), (12, 16, 0.825)]
