@@ -41,9 +41,11 @@
 // so one packed fused multiply-add per cell forms H_diag + S for both
 // sequences, with no byte permute.  All lanes read the same row pair, so the
 // addresses fall in one 208-byte row pair of each table (two codes share a
-// pair of 32-bit banks when they are 16 apart).  The next strip's rows are
-// copied in during the current strip's last chunks, one or two dwords per
-// lane per chunk, so the copy holds few registers.
+// pair of 32-bit banks when they are 16 apart).  Each column's entries are
+// read while the previous column is computed (sweep_chunk_ahead), so the
+// LDS latency hides behind a column of arithmetic.  The next strip's rows
+// are copied in during the current strip's last chunks, one or two dwords
+// per lane per chunk, so the copy holds few registers.
 #include "internal.h"
 #include "packed16.h"
 
