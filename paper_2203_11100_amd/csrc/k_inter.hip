@@ -160,19 +160,17 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
       for (int y = 0; y < kPer; ++y)
         st[y] = st_src[min((kPer * max(x_st, 0) + y) * 64 + lane, kSlot - 1)];
       __builtin_amdgcn_sched_barrier(0);   // keep the loads ahead of the compute
-      uint32_t out_h[4], out_f[4];
-      sweep_chunk_ahead<R, true>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+      // the strip's bottom row, (H, F) per column, stored as each column is
+      // done (column jj at 8 jj bytes of the lane's 32-byte chunk entry)
+      uint2* pbd = reinterpret_cast<uint2*>(rbb + (size_t)(c * 64 + lane) * 2);
+      const bool keep = s < S - 1;
+      sweep_chunk_ahead<R, true>(H, E, hdiag, up_h, up_f, best, go, ge,
                                  [&](int jj, int k2, uint2& A, uint2& B) {
         read_pair(slot, rr, jj, k2, A, B);
+      }, [&](int jj, uint32_t h, uint32_t f) {
+        if (keep) pbd[jj] = make_uint2(h, f);
+        else pbd[jj] = make_uint2(0, 0);   // the last strip leaves zeros for the next search
       });
-      uint4* pbd = rbb + (size_t)(c * 64 + lane) * 2;
-      if (s < S - 1) {
-        pbd[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
-        pbd[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
-      } else {   // the last strip leaves the buffer zeroed for the next search
-        pbd[0] = make_uint4(0, 0, 0, 0);
-        pbd[1] = make_uint4(0, 0, 0, 0);
-      }
       if (stage) {
 #pragma unroll
         for (int y = 0; y < kPer; ++y) {

@@ -125,12 +125,15 @@ __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], 
 //                table's two (1, S) dwords, one fused multiply-add per cell
 //                forming H_diag + S (see hfma); without, a = the two rows'
 //                packed scores, added to H_diag (b unused)
-template <int R, bool kSplit, class ProfPair>
+//   emit(jj, h, f)  takes H and F of the strip's bottom row at column jj as
+//                soon as the column is done (stored at once, the registers
+//                of the four columns' results are not held to the chunk's end)
+template <int R, bool kSplit, class ProfPair, class Emit>
 __device__ __forceinline__ void sweep_chunk_ahead(uint32_t (&H)[R], uint32_t (&E)[R],
                                                   uint32_t& hdiag, const uint32_t (&up_h)[4],
-                                                  const uint32_t (&up_f)[4], uint32_t (&out_h)[4],
-                                                  uint32_t (&out_f)[4], uint32_t& best,
-                                                  uint32_t go, uint32_t ge, ProfPair prof_pair) {
+                                                  const uint32_t (&up_f)[4], uint32_t& best,
+                                                  uint32_t go, uint32_t ge, ProfPair prof_pair,
+                                                  Emit emit) {
   static_assert(R % 2 == 0, "rows are taken in pairs");
   // VALU and SALU may cross the scheduling barriers; LDS reads may not
   constexpr int kMayCross = 0x0002 | 0x0004;
@@ -163,8 +166,7 @@ __device__ __forceinline__ void sweep_chunk_ahead(uint32_t (&H)[R], uint32_t (&E
       H[2 * k2 + 1] = h1;
       best = hmax3(best, h0, h1);
     }
-    out_h[jj] = H[R - 1];
-    out_f[jj] = F;
+    emit(jj, H[R - 1], F);
   }
 }
 
