@@ -113,12 +113,16 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
         const bool stage = more && x_st >= 0 && x_st * 64 + lane < kSlot;
         uint32_t st = 0;
         if (stage) st = prof[(size_t)(s + Wu) * kSlot + x_st * 64 + lane];
-        uint32_t out_h[4], out_f[4];
+        // the strip's bottom row, (H, F) per column, stored as each column is
+        // done (column jj at 8 jj bytes of the lane's 32-byte chunk entry);
+        // the last strip's are stored too, unread (a first strip never reads
+        // the workgroup's buffer), so the chunk has no branch
+        uint2* pbd = reinterpret_cast<uint2*>(rbb + (size_t)(c * 64 + lane) * 2);
         // residue bytes hold 8 x code, the byte offset of the code's dword
         // pair in a row pair: one 64-bit LDS read gives two rows (reading a
         // column ahead, as the single-query kernel does, measured 2 % slower
         // here: one table, half the reads to hide)
-        sweep_chunk<R>(H, E, hdiag, up_h, up_f, out_h, out_f, best, go, ge,
+        sweep_chunk<R>(H, E, hdiag, up_h, up_f, best, go, ge,
                        [&](int jj, uint32_t (&p)[R]) {
           const uint2* pc = reinterpret_cast<const uint2*>(
               reinterpret_cast<const char*>(slot) + ((rr >> (8 * jj)) & 0xffu));
@@ -128,12 +132,7 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
             p[2 * k2] = A.x;
             p[2 * k2 + 1] = A.y;
           }
-        });
-        if (s < S - 1) {
-          uint4* p = rbb + (size_t)(c * 64 + lane) * 2;
-          p[0] = make_uint4(out_h[0], out_f[0], out_h[1], out_f[1]);
-          p[1] = make_uint4(out_h[2], out_f[2], out_h[3], out_f[3]);
-        }
+        }, [&](int jj, uint32_t h, uint32_t f) { pbd[jj] = make_uint2(h, f); });
         if (stage) lprof[w][(q + 1) & 1][x_st * 64 + lane] = st;
         __syncthreads();
       }
@@ -187,7 +186,8 @@ hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t 
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return launch_rw<r, w>(grid, a, s);
   SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
-  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(12, 16)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(20, 12) SWDB_CASE(12, 16) \
+  SWDB_CASE(14, 16)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
 }
@@ -196,7 +196,8 @@ int batch_workgroups_per_cu(int R, int W) {
 #define SWDB_CASE(r, w) \
   if (R == r && W == w) return occupancy<r, w>();
   SWDB_CASE(16, 4) SWDB_CASE(16, 8) SWDB_CASE(16, 12) SWDB_CASE(32, 4) SWDB_CASE(32, 8)
-  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(12, 16)
+  SWDB_CASE(12, 12) SWDB_CASE(14, 12) SWDB_CASE(18, 12) SWDB_CASE(20, 12) SWDB_CASE(12, 16) \
+  SWDB_CASE(14, 16)
 #undef SWDB_CASE
   return 1;
 }

@@ -85,12 +85,13 @@ __device__ __forceinline__ uint32_t cell(uint32_t& hd, uint32_t& H, uint32_t& E,
 //   hdiag        H of the row above the strip at the column before the chunk;
 //                leaves as that of the chunk's last column
 //   up_h, up_f   H and F of the row above the strip, per column
-//   out_h, out_f H and F of the strip's bottom row, per column
-template <int R, class Prof>
+//   emit(jj, h, f)  takes H and F of the strip's bottom row at column jj as
+//                soon as the column is done
+template <int R, class Prof, class Emit>
 __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], uint32_t& hdiag,
                                             const uint32_t (&up_h)[4], const uint32_t (&up_f)[4],
-                                            uint32_t (&out_h)[4], uint32_t (&out_f)[4],
-                                            uint32_t& best, uint32_t go, uint32_t ge, Prof prof) {
+                                            uint32_t& best, uint32_t go, uint32_t ge, Prof prof,
+                                            Emit emit) {
   static_assert(R % 2 == 0, "rows are taken in pairs for the maximum");
 #pragma unroll
   for (int jj = 0; jj < 4; ++jj) {
@@ -108,8 +109,7 @@ __device__ __forceinline__ void sweep_chunk(uint32_t (&H)[R], uint32_t (&E)[R], 
       if (k & 1) best = hmax3(best, hprev, h);
       else hprev = h;
     }
-    out_h[jj] = H[R - 1];
-    out_f[jj] = F;
+    emit(jj, H[R - 1], F);
   }
 }
 

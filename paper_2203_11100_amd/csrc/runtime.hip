@@ -322,12 +322,12 @@ struct Sched {
 constexpr Sched kScheds[] = {{20, 12, 0.780}, {18, 12, 0.831}, {16, 12, 0.833}, {14, 12, 0.810},
                              {12, 12, 0.805}, {14, 16, 0.868}, {12, 16, 0.864}};
 
-// The batched kernel's fitted schedules (the 20 x 12 and 14 x 16 forms
-// spill registers there); efficiencies measured the same way on the
-// single-query kernel when it, like the batched kernel, read each column's
-// profile at the column's start.
-constexpr Sched kBatchScheds[] = {{18, 12, 0.851}, {16, 12, 0.830}, {14, 12, 0.812},
-                                  {12, 12, 0.781}, {12, 16, 0.832}};
+// The batched kernel's fitted schedules, with relative efficiencies from the
+// batched workload (220 queries, every form forced): GCUPS x padded rows /
+// rows over its pairs, divided by 10,000.
+constexpr Sched kBatchScheds[] = {{20, 12, 0.842}, {18, 12, 0.824}, {16, 12, 0.771},
+                                  {14, 12, 0.808}, {12, 12, 0.775}, {14, 16, 0.842},
+                                  {12, 16, 0.839}};
 
 // A bin of C chunks takes ceil(S / W) rounds of its S = ceil(m / R) strips,
 // each round C supersteps of W waves' chunks, so its time is proportional
@@ -617,12 +617,13 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
     }
   }
   if (db->opt_rows == 12 || db->opt_rows == 14 || db->opt_rows == 16 || db->opt_rows == 18 ||
-      db->opt_rows == 32)
+      db->opt_rows == 20 || db->opt_rows == 32)
     R = db->opt_rows;
   if (db->opt_waves == 4 || db->opt_waves == 8 || db->opt_waves == 12 || db->opt_waves == 16)
     W = db->opt_waves;
-  if (W == 16 && R != 12) R = 12;                  // 16 waves: 12-row strips
   if (W == 12 && R == 32) W = 8;                   // no 12-wave form of 32 rows
+  if (R == 20) W = 12;                             // 20 rows: 12 waves only
+  if (W == 16 && R != 12 && R != 14) R = 12;       // 16 waves: 12- or 14-row strips
   if (W != 12 && W != 16 && R != 16 && R != 32) R = 16;
   std::vector<int64_t> qv(qoffs, qoffs + nq + 1);
   if (B.valid && B.qoffs == qv && memcmp(&B.mat, &mat, sizeof(mat)) == 0 && B.go == go &&

@@ -397,7 +397,8 @@ def test_batch_matches_oracle(sw, graphs):
 
 
 @pytest.mark.parametrize("rows,waves", [(16, 4), (16, 8), (16, 12), (32, 4), (32, 8),
-                                        (12, 12), (14, 12), (18, 12), (12, 16)])
+                                        (12, 12), (14, 12), (18, 12), (20, 12), (12, 16),
+                                        (14, 16)])
 def test_batch_strip_options(sw, rows, waves):
     res, offs = _ragged_db(22)
     qs = _queries(23, [300, 280, 90, 31])
