@@ -158,8 +158,8 @@ enum sw_option {
                              schedules' measured efficiencies), 12, 14, 16,
                              18, 20 (with 12 waves; 12 and 14 also with 16;
                              16 otherwise), 32 (not with 12 or 16 waves);
-                             batched searches: 12, 14, 16, 18 with 12 waves,
-                             12 with 16, 16 or 32 otherwise, auto fitted to
+                             batched searches: 12 .. 20 with 12 waves, 12 and
+                             14 with 16, 16 or 32 otherwise, auto fitted to
                              the pairs' lengths */
   SW_OPT_WAVES = 4,       /* inter-task waves per workgroup: 0 (auto), 1, 2, 4, 8, 12,
                              16 (12 not with 32 rows; 16 with 12 or 14 rows,
@@ -202,9 +202,10 @@ int sw_get_stats(sw_db* db, sw_stats* out);
  * around the kernels, and keeps the candidate with the highest GCUPS.
  * Later searches on the handle (and contexts created afterwards) use the
  * tuned entry of their query's bucket unless SW_OPT_ROWS / SW_OPT_WAVES are
- * set.  The candidate (0, 0) is the schedule fitted to each query's length
- * (single queries; 16 rows and 12 waves in batched searches).  Takes about a second on a 200,000-sequence database.  `report` may
- * be NULL.  Errors leave the handle untuned. */
+ * set.  The candidate (0, 0) is the schedule fitted to the query lengths
+ * (each query's in single searches, the pairs' in batched ones).  Takes
+ * about a second on a 200,000-sequence database.  `report` may be NULL.
+ * Errors leave the handle untuned. */
 #define SW_TUNE_BUCKETS 4
 #define SW_TUNE_CANDIDATES 4
 typedef struct sw_tune_report {
