@@ -8,7 +8,9 @@ penalties above 2048 passed as 2048.  The claim: a sequence whose true score
 is below L comes out exact, and one whose score is L or more comes out >= L.
 This model runs the same operations with numpy float16 (whose add, subtract
 and maximum of integers of magnitude < 2^24 round once, as the hardware's
-do) over a batch of sequences, and compares with the oracle on cases built
+do; the single-query kernel forms H_diag + S as a fused multiply-add
+(S, 1) * (1, S') + H_diag, whose products by 1 are exact, so it rounds once
+exactly as this add does) over a batch of sequences, and compares with the oracle on cases built
 to straddle the limit: planted matches scoring 1,900..2,400, a matrix with
 entries up to 127, gap penalties above 2048.
 """
