@@ -237,8 +237,11 @@ def test_planted_overflow_in_short_bins(sw):
     assert (got == _oracle(q, res, offs)).all()
 
 
-@pytest.mark.parametrize("gaps", [(0, 0), (5, 5), (11, 1), (40, 1), (1000, 1000), (12, 2)])
+@pytest.mark.parametrize("gaps", [(0, 0), (5, 5), (11, 1), (40, 1), (1000, 1000), (12, 2),
+                                  (3000, 2500), (5000, 1)])
 def test_gap_penalties(sw, gaps):
+    """Gap penalties from none to above the binary16 exact range (passed to
+    the packed kernels as 2048)."""
     res, offs = _ragged_db(4)
     q = swinputs.random_residues(180, np.random.default_rng(9))
     say("gaps", gaps)
