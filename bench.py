@@ -35,8 +35,8 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection code it was taken on: bench
 # reports null when the digest of that code (comments removed) differs.
-TRAFFIC = {"bytes_per_launch": 2.3967e+10, "fetch_bytes": 60.06e9, "write_bytes": 419.27e9,
-           "launches": 20, "sources_sha256": "931d9a3e650d174697322d94b98a23bae9ab6d7fb11526a5e36b3dec6c0b6770"}
+TRAFFIC = {"bytes_per_launch": 2.1985e+10, "fetch_bytes": 56.10e9, "write_bytes": 383.59e9,
+           "launches": 20, "sources_sha256": "f2d55c5d1b8e9c582d6b090af8b69b59bd03ffbe6b2832eb221a9cb1238e2292"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
 # instruction x 2.4 GHz = 78.64 T half-ops/s

@@ -163,14 +163,17 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
       // the strip's bottom row, (H, F) per column, stored as each column is
       // done (column jj at 8 jj bytes of the lane's 32-byte chunk entry)
       uint2* pbd = reinterpret_cast<uint2*>(rbb + (size_t)(c * 64 + lane) * 2);
-      const bool keep = s < S - 1;
       sweep_chunk_ahead<R, true>(H, E, hdiag, up_h, up_f, best, go, ge,
                                  [&](int jj, int k2, uint2& A, uint2& B) {
         read_pair(slot, rr, jj, k2, A, B);
-      }, [&](int jj, uint32_t h, uint32_t f) {
-        if (keep) pbd[jj] = make_uint2(h, f);
-        else pbd[jj] = make_uint2(0, 0);   // the last strip leaves zeros for the next search
-      });
+      }, [&](int jj, uint32_t h, uint32_t f) { pbd[jj] = make_uint2(h, f); });
+      // the last strip leaves zeros for the next search (the same lane's later
+      // stores to the same addresses land last)
+      if (s == S - 1) {
+        uint4* pz = rbb + (size_t)(c * 64 + lane) * 2;
+        pz[0] = make_uint4(0, 0, 0, 0);
+        pz[1] = make_uint4(0, 0, 0, 0);
+      }
       if (stage) {
 #pragma unroll
         for (int y = 0; y < kPer; ++y) {

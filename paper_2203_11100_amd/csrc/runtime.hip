@@ -306,7 +306,7 @@ int tune_bucket(int m) {
 }
 
 // Default schedule of the inter-task kernels: 16-row strips and 12 waves per
-// bin (three waves per SIMD at 134 VGPRs; measured faster than 32 x 8 for
+// bin (three waves per SIMD at 136 VGPRs; measured faster than 32 x 8 for
 // every query length of the plain workload and for the batched one).
 constexpr int kDefaultRows = 16, kDefaultWaves = 12;
 
@@ -319,8 +319,8 @@ struct Sched {
   int R, W;
   double eff;
 };
-constexpr Sched kScheds[] = {{20, 12, 0.780}, {18, 12, 0.831}, {16, 12, 0.833}, {14, 12, 0.810},
-                             {12, 12, 0.805}, {14, 16, 0.868}, {12, 16, 0.864}};
+constexpr Sched kScheds[] = {{20, 12, 0.819}, {18, 12, 0.809}, {16, 12, 0.815}, {14, 12, 0.796},
+                             {12, 12, 0.792}, {14, 16, 0.868}, {12, 16, 0.850}};
 
 // The batched kernel's fitted schedules, with relative efficiencies from the
 // batched workload (220 queries, every form forced): GCUPS x padded rows /
