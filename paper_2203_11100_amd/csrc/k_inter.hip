@@ -141,6 +141,11 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
     uint32_t hdiag = 0;
     const uint32_t* slot = &lprof[w][q & 1][0];
     const bool more = q + 1 < my_rounds;
+    // no scalar load may be pending when the chunk loop starts: scalar loads
+    // return out of order, so one pending at the loop's entry would make the
+    // compiler wait for all LDS reads at every chunk's start instead of only
+    // for the first row pair's
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), other counters untouched
     for (int c = 0; c < C; ++c) {
       const uint2 rr = rr_n;
       const uint32_t up_h[4] = {b0_n.x, b0_n.z, b1_n.x, b1_n.z};

@@ -319,8 +319,8 @@ struct Sched {
   int R, W;
   double eff;
 };
-constexpr Sched kScheds[] = {{20, 12, 0.819}, {18, 12, 0.809}, {16, 12, 0.815}, {14, 12, 0.796},
-                             {12, 12, 0.792}, {14, 16, 0.868}, {12, 16, 0.850}};
+constexpr Sched kScheds[] = {{20, 12, 0.835}, {18, 12, 0.821}, {16, 12, 0.838}, {14, 12, 0.810},
+                             {12, 12, 0.814}, {14, 16, 0.868}, {12, 16, 0.863}};
 
 // The batched kernel's fitted schedules, with relative efficiencies from the
 // batched workload (220 queries, every form forced): GCUPS x padded rows /

@@ -100,8 +100,8 @@ def test_consecutive_searches_change_schedule(sw):
 
 
 # (rows, waves, efficiency per strip slot) of the library's fitted schedules
-_SCHEDS = [(20, 12, 0.819), (18, 12, 0.809), (16, 12, 0.815), (14, 12, 0.796),
-           (12, 12, 0.792), (14, 16, 0.868), (12, 16, 0.850)]
+_SCHEDS = [(20, 12, 0.835), (18, 12, 0.821), (16, 12, 0.838), (14, 12, 0.810),
+           (12, 12, 0.814), (14, 16, 0.868), (12, 16, 0.863)]
 
 
 def _fit_schedule(m):
