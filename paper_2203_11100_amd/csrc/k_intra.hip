@@ -311,6 +311,10 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
 #pragma unroll
       for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
       uint32_t hdiag = 0, code = kPadPair, hbot = 0, fbot = 0;
+      // nothing pending at the chunk loop's entry: a scalar load pending
+      // there (they return out of order) would make every step wait for the
+      // next step's profile reads as well as its own
+      __builtin_amdgcn_s_waitcnt(0);   // vmcnt(0) expcnt(0) lgkmcnt(0)
       for (int c = 0; c < C2; ++c) {
         uint32_t fcode = fcode_n, fh = fh_n, ff = ff_n;
         if (c + 1 < C2) fetch(p, c + 1);
