@@ -35,8 +35,8 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection code it was taken on: bench
 # reports null when the digest of that code (comments removed) differs.
-TRAFFIC = {"bytes_per_launch": 2.2671e+10, "fetch_bytes": 57.48e9, "write_bytes": 395.93e9,
-           "launches": 20, "sources_sha256": "6978aa89db5c6a3bc2cbf3ebb1761200f566dad4e540c85913917ebec9940eff"}
+TRAFFIC = {"bytes_per_launch": 2.2669e+10, "fetch_bytes": 57.41e9, "write_bytes": 395.98e9,
+           "launches": 20, "sources_sha256": "1cef97e947cfb1b4de9f45a250932355328ad55351670f2e10b8636cf8744fba"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
 # instruction x 2.4 GHz = 78.64 T half-ops/s

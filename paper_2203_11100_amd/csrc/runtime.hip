@@ -325,9 +325,9 @@ constexpr Sched kScheds[] = {{20, 12, 0.835}, {18, 12, 0.821}, {16, 12, 0.838}, 
 // The batched kernel's fitted schedules, with relative efficiencies from the
 // batched workload (220 queries, every form forced): GCUPS x padded rows /
 // rows over its pairs, divided by 10,000.
-constexpr Sched kBatchScheds[] = {{20, 12, 0.842}, {18, 12, 0.824}, {16, 12, 0.771},
-                                  {14, 12, 0.808}, {12, 12, 0.775}, {14, 16, 0.842},
-                                  {12, 16, 0.839}};
+constexpr Sched kBatchScheds[] = {{20, 12, 0.855}, {18, 12, 0.848}, {16, 12, 0.833},
+                                  {14, 12, 0.845}, {12, 12, 0.834}, {14, 16, 0.843},
+                                  {12, 16, 0.861}};
 
 // A bin of C chunks takes ceil(S / W) rounds of its S = ceil(m / R) strips,
 // each round C supersteps of W waves' chunks, so its time is proportional
