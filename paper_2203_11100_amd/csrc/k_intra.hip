@@ -271,19 +271,22 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
     const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
     const int T_total = q_last * C2 + kSkew * w_last + C2;
 
-    uint32_t fcode_n = kPadPair, fh_n = 0, ff_n = 0;
+    // the next chunk's inputs, loaded a chunk ahead: the raw residue bytes
+    // and the row above, every load issued (its index clamped into the
+    // sequence or the scratch row), the padding chosen and the codes packed
+    // where they are used, so no load is waited for before then
+    uint32_t ca_n = SW_PAD_CODE, cb_n = SW_PAD_CODE, fh_n = 0, ff_n = 0;
+    bool va_n = false, vb_n = false, vr_n = false;
     auto fetch = [&](int p, int c) {
       const int jf = c * 64 + lane;
-      const uint32_t ca = jf < na ? (uint32_t)sqa[jf] : (uint32_t)SW_PAD_CODE;
-      const uint32_t cb = jf < nb ? (uint32_t)sqb[jf] : (uint32_t)SW_PAD_CODE;
-      fcode_n = ca * kCodeBytes | (cb * kCodeBytes) << 16;
-      fh_n = 0;
-      ff_n = 0;
-      if (p > 0 && jf < n) {
-        const int2 v = rb[jf];
-        fh_n = (uint32_t)v.x;
-        ff_n = (uint32_t)v.y;
-      }
+      ca_n = sqa[min(jf, na - 1)];
+      cb_n = sqb[min(jf, max(nb - 1, 0))];
+      const int2 v = rb[min(jf, n - 1)];
+      fh_n = (uint32_t)v.x;
+      ff_n = (uint32_t)v.y;
+      va_n = jf < na;
+      vb_n = jf < nb;
+      vr_n = p > 0 && jf < n;
     };
 
     uint32_t best = 0;
@@ -316,7 +319,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
       // next step's profile reads as well as its own
       __builtin_amdgcn_s_waitcnt(0);   // vmcnt(0) expcnt(0) lgkmcnt(0)
       for (int c = 0; c < C2; ++c) {
-        uint32_t fcode = fcode_n, fh = fh_n, ff = ff_n;
+        uint32_t fcode = (va_n ? ca_n : (uint32_t)SW_PAD_CODE) * kCodeBytes |
+                         ((vb_n ? cb_n : (uint32_t)SW_PAD_CODE) * kCodeBytes) << 16;
+        uint32_t fh = vr_n ? fh_n : 0, ff = vr_n ? ff_n : 0;
         if (c + 1 < C2) fetch(p, c + 1);
         else if (more) fetch(p + W2, 0);
         uint32_t collh = 0, collf = 0;
