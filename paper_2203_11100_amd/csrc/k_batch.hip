@@ -102,9 +102,9 @@ __global__ __launch_bounds__(64 * W) void k_batch_f16(BatchArgs a) {
       const uint32_t* slot = &lprof[w][q & 1][0];
       const bool more = q + 1 < my_rounds;
       // nothing may be pending when the chunk loop starts: the compiler
-      // merges the loop's entry with its back edge, and a load pending on
-      // entry made every chunk wait for all memory operations, the prefetch
-      // it had just issued included, before its first cell
+      // merges the loop's entry with its back edge, so a load pending on
+      // entry would make every chunk wait for all memory operations, the
+      // prefetch it has just issued included, before its first cell
       __builtin_amdgcn_s_waitcnt(0);   // vmcnt(0) expcnt(0) lgkmcnt(0)
       for (int c = 0; c < C; ++c) {
         const uint32_t rr = rr_n;
