@@ -325,16 +325,25 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
         if (c + 1 < C2) fetch(p, c + 1);
         else if (more) fetch(p + W2, 0);
         uint32_t collh = 0, collf = 0;
+        // the codes of step tau + 1 are those of step tau shifted one lane
+        // (the inputs shifted in with them), so each step's profile reads are
+        // issued a step ahead; the chunk's first step reads at its start.  The
+        // extra read after the last step is of a valid code and unused.
+        uint32_t code_c = (uint32_t)shr_in((int)code, (int)fcode);
+        fcode = (uint32_t)shl_in((int)fcode, (int)kPadPair);
+        PV va = *reinterpret_cast<const PV*>(lbase + (code_c & 0xffffu));
+        PV vb = *reinterpret_cast<const PV*>(lbase + (code_c >> 16));
 #pragma unroll 2
         for (int tau = 0; tau < 64; ++tau) {
-          code = (uint32_t)shr_in((int)code, (int)fcode);
+          const uint32_t code_n = (uint32_t)shr_in((int)code_c, (int)fcode);
+          fcode = (uint32_t)shl_in((int)fcode, (int)kPadPair);
+          const PV va_n = *reinterpret_cast<const PV*>(lbase + (code_n & 0xffffu));
+          const PV vb_n = *reinterpret_cast<const PV*>(lbase + (code_n >> 16));
+          code = code_c;
           const uint32_t hup = (uint32_t)shr_in((int)hbot, (int)fh);
           const uint32_t fup = (uint32_t)shr_in((int)fbot, (int)ff);
-          fcode = (uint32_t)shl_in((int)fcode, (int)kPadPair);
           fh = (uint32_t)shl_in((int)fh, 0);
           ff = (uint32_t)shl_in((int)ff, 0);
-          const PV va = *reinterpret_cast<const PV*>(lbase + (code & 0xffffu));
-          const PV vb = *reinterpret_cast<const PV*>(lbase + (code >> 16));
           uint32_t pr[R];
 #pragma unroll
           for (int j = 0; j < RP; ++j) {
@@ -356,6 +365,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
           fbot = F;
           collh = (uint32_t)shl_in((int)collh, (int)hbot);
           collf = (uint32_t)shl_in((int)collf, (int)fbot);
+          code_c = code_n;
+          va = va_n;
+          vb = vb_n;
         }
         const int jo = c * 64 + lane - 63;
         if (!last_pass && jo >= 0 && jo < n) rb[jo] = make_int2((int)collh, (int)collf);
