@@ -39,14 +39,21 @@ TRAFFIC = {"bytes_per_launch": 2.2669e+10, "fetch_bytes": 57.41e9, "write_bytes"
            "launches": 20, "sources_sha256": "1cef97e947cfb1b4de9f45a250932355328ad55351670f2e10b8636cf8744fba"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 halves of a packed 16-bit
-# instruction x 2.4 GHz = 78.64 T half-ops/s
+# instruction x 2.4 GHz = 78.64 T packed 16-bit lane-ops/s
 PEAK_HALF_TOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-# Packed binary16 instructions per cell pair of the recurrence on gfx950, as
-# half-ops per cell: 1 fused multiply-add forming H_diag + S for both halves
-# (the profile dwords hold (S, 1) and (1, S)), 3 subtract and 3 three-input
-# max for the cell, 1/2 three-input max for the running maximum (two rows per
-# op): the algorithm's own work, no packing or address arithmetic
-OPS_PER_CELL = 7.5
+# Algorithmic integer operations per cell of Gotoh's recurrence: 1 add
+# (H_diag + S), 3 max (E, F, 0), 1 max (running best), 1 subtract (H - open),
+# 2 subtract (E - extend, F - extend), 2 max (new E, new F).  The roofline
+# fraction `frac` counts these 10 per cell against the packed 16-bit peak.
+OPS_PER_CELL = 10
+# Packed binary16 instructions the inter-task kernel issues per cell (half-ops
+# per cell): 1 fused multiply-add forming H_diag + S for both halves (the
+# profile dwords hold (S, 1) and (1, S)), 3 subtract and 3 three-input max for
+# the cell, 1/2 three-input max for the running maximum (two rows per op).  A
+# three-input max does two of the 10 algorithmic maxima in one issue slot, so
+# 10 ops take 7.5 slots and `frac` can exceed 1; `frac_issue` is the fraction
+# of the issue slots the kernel's own instruction count needs.
+ISSUE_PER_CELL = 7.5
 
 
 def code_text(src):
@@ -167,15 +174,17 @@ def main():
     n_launch = max(st["n_inter_launches"], 1)
     inter_s = st["ms_inter"] / 1e3
     achieved = st["inter_cells"] * OPS_PER_CELL / inter_s / 1e12 if inter_s > 0 else None
+    issued = st["inter_cells"] * ISSUE_PER_CELL / inter_s / 1e12 if inter_s > 0 else None
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_HALF_TOPS, "unit": "Tops/s",
             "frac": (achieved / PEAK_HALF_TOPS) if achieved else None,
+            "frac_issue": (issued / PEAK_HALF_TOPS) if issued else None,
+            "ops_per_cell": OPS_PER_CELL, "issue_per_cell": ISSUE_PER_CELL,
             "traffic": measured_traffic(),
             "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, mean over the "
                             "step's 20 launches)",
             "kernel": "k_inter_f16 (rows, waves fitted per query; last query: %d, %d)"
                       % (st["rows"], st["waves"]),
-            "avg_launch_ms": st["ms_inter"] / n_launch,
-            "ops_per_cell": OPS_PER_CELL}
+            "avg_launch_ms": st["ms_inter"] / n_launch}
     result = {
         "metric": METRIC, "value": gcups, "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,

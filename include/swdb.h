@@ -19,10 +19,18 @@
  * evaluated in unbounded integers.  Internally most cells are computed in
  * packed IEEE half precision, which is exact for integers up to 2048; any
  * sequence whose half-precision score reaches the rescoring limit (at most
- * 2048) is rescored exactly in 32-bit integer arithmetic, and sequences
- * at least `long_threshold` residues long are scored by a 32-bit intra-task
- * (anti-diagonal wavefront) kernel (paper section 2.3: inter-task or
- * intra-task parallelism depending on the sequence length).
+ * 2048) is rescored exactly in 32-bit integer arithmetic.  Which kernel
+ * scores a sequence depends on its length (paper section 2.3: inter-task or
+ * intra-task parallelism depending on the sequence length):
+ *  - shorter than `long_threshold`: the packed half-precision inter-task
+ *    kernel (two sequences per lane);
+ *  - single searches, at least `long_threshold`: an anti-diagonal wavefront
+ *    (intra-task) kernel computing two such sequences at once in the two
+ *    packed half-precision halves of every register, with the same exact
+ *    rescoring;
+ *  - batched searches: sequences below 4 x `long_threshold` go through the
+ *    packed batched inter-task kernel (two queries per lane), longer ones
+ *    through the 32-bit intra-task kernel.
  *
  * Conventions (all entry points):
  *  - Residue codes are bytes 0..23 in BLOSUM order
@@ -95,7 +103,9 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
 /* Releases the handle and all its device memory; NULL is a no-op. */
 void sw_db_free(sw_db* db);
 
-/* Database statistics; any output pointer may be NULL. */
+/* Database statistics; any output pointer may be NULL.  n_long is the
+ * number of sequences at or above the long threshold (the intra-task
+ * kernel's list). */
 int sw_db_info(const sw_db* db, int64_t* n_seqs, int64_t* n_residues, int32_t* max_len,
                int64_t* n_long);
 
@@ -122,7 +132,10 @@ int sw_search_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
                     int32_t* d_out_scores, void* hip_stream);
 
 /* sw_search_batch: many queries against the resident database in one
- * persistent launch.  Queries are sorted by length and paired, two queries
+ * persistent launch: the same per-sequence scores as one sw_search per query
+ * (paper section 4.1 searches 20 queries against one database; section 2.2,
+ * case (b): every query against every database sequence, each pair an
+ * independent alignment matrix).  Queries are sorted by length and paired, two queries
  * per 32-bit register lane; the work list of (query pair, half bin) items is
  * drained costliest first by a fixed grid of workgroups.  Repeating a batch
  * with the same query lengths, matrix, gaps and buffers replays a captured
@@ -135,7 +148,12 @@ int sw_search_batch(sw_db* db, const uint8_t* queries, const int64_t* query_offs
                     int32_t n_queries, const int8_t* matrix, int32_t gap_open,
                     int32_t gap_extend, int32_t* out_scores);
 
-/* sw_search_batch_async: device queries/outputs, host query_offsets. */
+/* sw_search_batch_async: device queries/outputs, host query_offsets.
+ *   d_queries    : device, uint8_t[query_offsets[n_queries]] (codes not
+ *                  validated on the device, as for sw_search_async).
+ *   d_out_scores : device, int32_t[n_queries * n_seqs].
+ * The device buffers' sizes cannot be checked here; the caller guarantees
+ * them (the Python binding checks them before the call). */
 int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* query_offsets,
                           int32_t n_queries, const int8_t* matrix, int32_t gap_open,
                           int32_t gap_extend, int32_t* d_out_scores, void* hip_stream);

@@ -45,6 +45,44 @@ def _matrix(matrix) -> np.ndarray:
     return m
 
 
+def _check_tensor(t, name: str, dtype_name: str, min_numel: int):
+    """Rejects a device buffer the C ABI cannot check itself: not a tensor,
+    wrong dtype, non-contiguous or too small (ValueError).  Whether it is in
+    GPU memory is checked after every buffer's other properties."""
+    import torch
+    want = getattr(torch, dtype_name)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype != want:
+        raise ValueError("%s must be torch.%s, not %s" % (name, dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < min_numel:
+        raise ValueError("%s holds %d elements, needs at least %d" % (name, t.numel(), min_numel))
+
+
+def _check_on_gpu(**tensors):
+    for name, t in tensors.items():
+        if not t.is_cuda:
+            raise ValueError("%s must be in GPU memory" % name)
+
+
+def _check_search_args(d_query, d_out, n_seqs: int):
+    _check_tensor(d_query, "d_query", "uint8", 0)
+    _check_tensor(d_out, "d_out", "int32", n_seqs)
+    _check_on_gpu(d_query=d_query, d_out=d_out)
+
+
+def _check_batch_args(d_queries, qoffs: np.ndarray, d_out, n_seqs: int):
+    if qoffs.ndim != 1 or len(qoffs) < 1:
+        raise ValueError("query_offsets must be a 1-D array of n_queries + 1 offsets")
+    if qoffs[0] != 0 or (np.diff(qoffs) < 0).any():
+        raise ValueError("query_offsets must start at 0 and be non-decreasing")
+    _check_tensor(d_queries, "d_queries", "uint8", int(qoffs[-1]))
+    _check_tensor(d_out, "d_out", "int32", (len(qoffs) - 1) * n_seqs)
+    _check_on_gpu(d_queries=d_queries, d_out=d_out)
+
+
 def _stream_handle(stream) -> Optional[int]:
     if stream is None:
         import torch
@@ -153,6 +191,7 @@ class Database:
     def search_async(self, d_query, matrix, gap_open: int, gap_extend: int, d_out,
                      stream=None):
         """Device buffers (torch tensors): d_query uint8[m], d_out int32[n_seqs]."""
+        _check_search_args(d_query, d_out, self.n_seqs)
         m = _matrix(matrix)
         _native.check(_native.lib().sw_search_async(
             self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
@@ -174,6 +213,7 @@ class Database:
     def search_batch_async(self, d_queries, query_offsets, matrix, gap_open: int,
                            gap_extend: int, d_out, stream=None):
         qoffs = _i64(query_offsets)
+        _check_batch_args(d_queries, qoffs, d_out, self.n_seqs)
         m = _matrix(matrix)
         _native.check(_native.lib().sw_search_batch_async(
             self._h, _ptr(d_queries), _ptr(qoffs), len(qoffs) - 1, _ptr(m), gap_open,
@@ -221,6 +261,7 @@ class Context:
 
     def search_async(self, d_query, matrix, gap_open: int, gap_extend: int, d_out,
                      stream=None):
+        _check_search_args(d_query, d_out, self.n_seqs)
         m = _matrix(matrix)
         _native.check(_native.lib().sw_ctx_search_async(
             self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
@@ -229,6 +270,7 @@ class Context:
     def search_batch_async(self, d_queries, query_offsets, matrix, gap_open: int,
                            gap_extend: int, d_out, stream=None):
         qoffs = _i64(query_offsets)
+        _check_batch_args(d_queries, qoffs, d_out, self.n_seqs)
         m = _matrix(matrix)
         _native.check(_native.lib().sw_ctx_search_batch_async(
             self._h, _ptr(d_queries), _ptr(qoffs), len(qoffs) - 1, _ptr(m), gap_open,

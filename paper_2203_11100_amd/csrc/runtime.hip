@@ -37,23 +37,25 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(SW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Streams whose pending work may still use a searcher's buffers; a buffer
-// is only replaced after they drain (set by the owning searcher).
+// Work that may still use a searcher's buffers: its own two streams, and
+// the last piece of work it enqueued on a caller's stream, marked by an
+// event the searcher owns (recorded at the end of every call that enqueues
+// on a caller's stream).  The caller's stream handle itself is never kept:
+// the caller may destroy it once the call returns.  A buffer is only
+// replaced after this work drains.
 struct StreamSet {
-  hipStream_t s[3] = {nullptr, nullptr, nullptr};
-  bool used[3] = {false, false, false};   // the null stream is a valid entry
+  hipStream_t own[2] = {nullptr, nullptr};
+  hipEvent_t caller_done = nullptr;
+  bool caller_pending = false;
   bool any = false;
-  void set(int i, hipStream_t x) {
-    s[i] = x;
-    used[i] = true;
-  }
   void sync() const {
     if (!any) {
       (void)hipDeviceSynchronize();
       return;
     }
-    for (int i = 0; i < 3; ++i)
-      if (used[i]) (void)hipStreamSynchronize(s[i]);
+    for (hipStream_t s : own)
+      if (s) (void)hipStreamSynchronize(s);
+    if (caller_pending) (void)hipEventSynchronize(caller_done);
   }
 };
 
@@ -116,6 +118,11 @@ struct BatchPlan {
   swdb::DevBuf<int8_t> prof2;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the searcher's scratch buffers the captured graph's kernels address
+  // (long-sequence and rescoring rows, rescoring list, work counter, batched
+  // boundary rows): a searcher call that grows one of them frees the old
+  // block, so the graph is re-captured whenever one of these differs
+  const void* captured[5] = {};
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -173,6 +180,7 @@ struct Searcher {
   hipStream_t own_stream = nullptr; // host-buffer calls and batch graphs
   hipStream_t aux_stream = nullptr; // long-sequence kernel, overlapped
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_caller = nullptr;   // end of the last work enqueued on a caller's stream
   // timing: (kind, start, end) event pairs recorded since the last
   // sw_get_stats; events are recycled through `ev_pool`
   struct Timed { int kind; hipEvent_t a, b; };
@@ -213,7 +221,9 @@ void release_searcher(Searcher* db) {
   db->prof.release(); db->prof2.release(); db->prof3.release(); db->q_stage.release();
   db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
-  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out}) {
+  if (db->users.caller_pending) (void)hipEventSynchronize(db->ev_caller);
+  db->users.caller_pending = false;
+  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out, &db->ev_caller}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
@@ -276,13 +286,20 @@ int init_searcher(Searcher* S, DbData* d) {
   if ((e = hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipStreamCreateWithFlags(&S->aux_stream, hipStreamNonBlocking)) != hipSuccess)
     return hip_fail(e, "stream creation");
-  S->users.set(0, S->own_stream);
-  S->users.set(1, S->aux_stream);
+  S->users.own[0] = S->own_stream;
+  S->users.own[1] = S->aux_stream;
   S->users.any = true;
-  for (hipEvent_t* ev : {&S->ev_fork, &S->ev_join, &S->ev_in, &S->ev_out})
+  for (hipEvent_t* ev : {&S->ev_fork, &S->ev_join, &S->ev_in, &S->ev_out, &S->ev_caller})
     if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e, "event creation");
+  S->users.caller_done = S->ev_caller;
   return SW_OK;
+}
+
+// Marks the end of the work a call enqueued on the caller's stream s, so
+// later buffer replacements wait for it (without keeping s itself).
+void mark_caller_work(Searcher* S, hipStream_t s) {
+  if (hipEventRecord(S->ev_caller, s) == hipSuccess) S->users.caller_pending = true;
 }
 
 int validate_search(const Searcher* db, const void* query, int32_t m, const int8_t* matrix,
@@ -846,6 +863,9 @@ int run_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int3
     rc = enqueue_batch_kernels(db, os);
     if (rc != SW_OK) return rc;
   } else {
+    const void* scratch[5] = {db->rb_long.p, db->rb_resc.p, db->flags.p, db->counter.p,
+                              db->rb_batch.p};
+    if (B.exec && memcmp(scratch, B.captured, sizeof(scratch)) != 0) B.drop_graph();
     if (!B.exec) {
       if ((e = hipStreamBeginCapture(os, hipStreamCaptureModeThreadLocal)) != hipSuccess)
         return hip_fail(e, "graph capture");
@@ -859,6 +879,7 @@ int run_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int3
         B.drop_graph();
         return hip_fail(e, "graph instantiation");
       }
+      memcpy(B.captured, scratch, sizeof(scratch));
     }
     if ((e = hipGraphLaunch(B.exec, os)) != hipSuccess) return hip_fail(e, "graph launch");
   }
@@ -1000,9 +1021,9 @@ static int impl_search_async(swdb::Searcher* db, const uint8_t* d_query, int32_t
   DeviceGuard g(db->d->device);
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
-  db->users.set(2, reinterpret_cast<hipStream_t>(hip_stream));
   rc = enqueue_search(db, d_query, query_len, mat, gap_open, gap_extend, d_out_scores,
                       reinterpret_cast<hipStream_t>(hip_stream));
+  mark_caller_work(db, reinterpret_cast<hipStream_t>(hip_stream));
   if (rc == SW_OK) set_error("");
   return rc;
 }
@@ -1074,9 +1095,9 @@ static int impl_search_batch_async(swdb::Searcher* db, const uint8_t* d_queries,
   DeviceGuard g(db->d->device);
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
-  db->users.set(2, reinterpret_cast<hipStream_t>(hip_stream));
   rc = run_batch(db, d_queries, query_offsets, n_queries, mat, gap_open, gap_extend, d_out_scores,
                  reinterpret_cast<hipStream_t>(hip_stream));
+  mark_caller_work(db, reinterpret_cast<hipStream_t>(hip_stream));
   if (rc == SW_OK) set_error("");
   return rc;
 }

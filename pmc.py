@@ -10,14 +10,14 @@ Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
 block per run) each dispatch gets its counter value; dividing a search
 kernel's value by the copy kernel's value per MiB converts it into bytes.
 
-    python -m paper_2203_11100_amd.pmc [--queries 0,19] [--copy-mib 1024]
+    python pmc.py [--queries 0,19] [--copy-mib 1024]
 """
 import argparse
 import json
 import os
 import sys
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

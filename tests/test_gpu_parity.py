@@ -352,18 +352,10 @@ def test_long_mix_workload_scaled(sw):
     assert (got[2][w.planted] == diag).all()
 
 
-def test_full_size_plain_workload_sampled(sw):
-    """All 20 queries on the full 200,000-sequence database, in the launch
-    configuration the benchmark times; every score of a sample spanning the
-    length distribution (incl. the longest sequences) checked by the oracle,
-    plus properties that hold for every score."""
+def _plain_gpu_rows(sw, w):
+    """The 20 plain queries searched as the benchmark does: one asynchronous
+    search per query on the current stream, database resident."""
     import torch
-    w = swinputs.config("plain")
-    lens = np.diff(w.offsets)
-    order = np.argsort(-lens, kind="stable")
-    rng = np.random.default_rng(12)
-    ids = np.unique(np.concatenate([order[:6], order[-6:], rng.choice(w.n_seqs, 60, replace=False)]))
-    say("full plain workload: %d seqs, %d residues" % (w.n_seqs, w.n_residues))
     with sw.Database(w.residues, w.offsets) as db:
         outs = []
         for q in w.queries:
@@ -371,14 +363,58 @@ def test_full_size_plain_workload_sampled(sw):
             db.search_async(torch.from_numpy(q).cuda(), w.matrix, 10, 2, d_out)
             outs.append(d_out)
         torch.cuda.synchronize()
-        got = np.stack([o.cpu().numpy() for o in outs])
+        return np.stack([o.cpu().numpy() for o in outs])
+
+
+def _check_bounds(row, q, lens):
+    # every score: 0 <= s <= min(m, n) * 11 (the largest BLOSUM62 entry)
+    assert (row >= 0).all()
+    assert (row <= np.minimum(len(q), lens) * 11).all()
+
+
+def test_full_size_plain_workload_full_rows(sw):
+    """All 20 queries on the full 200,000-sequence database in the launch
+    configuration the benchmark times.  Every one of the 200,000 scores of
+    the five shortest queries (144..310 residues) is compared with the
+    oracle; the other queries are sampled across the length distribution
+    (the longest query's full row is the next test)."""
+    from conftest import workload, oracle_row
+    w = workload("plain")
+    lens = np.diff(w.offsets)
+    say("full plain workload: %d seqs, %d residues" % (w.n_seqs, w.n_residues))
+    got = _plain_gpu_rows(sw, w)
+    _PLAIN_GOT["rows"] = got
+    for qi in range(5):
+        want = oracle_row(w, w.queries[qi])
+        bad = np.nonzero(got[qi] != want)[0]
+        assert len(bad) == 0, (qi, bad[:5], got[qi][bad[:5]], want[bad[:5]])
+        say("query %d (m=%d): all %d scores equal the oracle" % (qi, len(w.queries[qi]), w.n_seqs))
+    order = np.argsort(-lens, kind="stable")
+    rng = np.random.default_rng(12)
+    ids = np.unique(np.concatenate([order[:6], order[-6:], rng.choice(w.n_seqs, 60, replace=False)]))
+    import oracle.cpu as ocpu
     for qi, q in enumerate(w.queries):
-        want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
-        assert (got[qi][ids] == want).all(), (qi, ids[got[qi][ids] != want][:5])
-        # every score: 0 <= s <= min(m, n) * 11, and at least the best single pair
-        assert (got[qi] >= 0).all()
-        assert (got[qi] <= np.minimum(len(q), lens) * 11).all()
-    say("sampled %d x %d scores ok" % (len(w.queries), len(ids)))
+        _check_bounds(got[qi], q, lens)
+        if qi >= 5:
+            want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
+            assert (got[qi][ids] == want).all(), (qi, ids[got[qi][ids] != want][:5])
+
+
+_PLAIN_GOT = {}
+
+
+def test_full_size_plain_workload_longest_query_full_row(sw):
+    """Every score of the longest plain query (5,478 residues) against the
+    full database, compared with the oracle."""
+    from conftest import workload, oracle_row
+    w = workload("plain")
+    got = _PLAIN_GOT.get("rows")
+    if got is None:
+        got = _plain_gpu_rows(sw, w)
+    say("longest plain query: oracle row of %d scores" % w.n_seqs)
+    want = oracle_row(w, w.queries[19])
+    bad = np.nonzero(got[19] != want)[0]
+    assert len(bad) == 0, (bad[:5], got[19][bad[:5]], want[bad[:5]])
 
 
 # --------------------------------------------------------------- batched form
@@ -429,10 +465,15 @@ def test_batch_long_and_rescoring_items(sw):
 
 def test_batch_graph_replays_with_eager_work_between(sw):
     """Replays of the captured batch graph, with single searches and host
-    synchronisation between them, each equal the eager result."""
+    synchronisation between them, each equal to the oracle.  The single
+    searches grow the handle's long-sequence scratch (about 100 long pairs
+    against the batch's 5 very long items), freeing the block the first
+    capture addressed: the graph must be re-captured, not replayed onto the
+    freed block (regression test for that use after free)."""
     import torch
     res, offs = _ragged_db(26)
     qs = _queries(27, [150, 400, 90, 260, 51])
+    want = np.stack([_oracle(q, res, offs) for q in qs])
     cat = torch.from_numpy(np.concatenate(qs)).cuda()
     qoffs = np.zeros(len(qs) + 1, np.int64)
     np.cumsum([len(q) for q in qs], out=qoffs[1:])
@@ -442,18 +483,16 @@ def test_batch_graph_replays_with_eager_work_between(sw):
         d_eager = torch.full((len(qs), db.n_seqs), -1, dtype=torch.int32, device="cuda")
         db.search_batch_async(cat, qoffs, B62, 10, 2, d_eager)
         torch.cuda.synchronize()
-        eager = d_eager.cpu().numpy()
+        assert (d_eager.cpu().numpy() == want).all()
         db.set_option(sw.SW_OPT_GRAPHS, 1)
         d_out = torch.full((len(qs), db.n_seqs), -1, dtype=torch.int32, device="cuda")
         for rep in range(4):
             d_out.fill_(-1)
             db.search_batch_async(cat, qoffs, B62, 10, 2, d_out)
             torch.cuda.synchronize()
-            assert (d_out.cpu().numpy() == eager).all(), rep
+            assert (d_out.cpu().numpy() == want).all(), rep
             single = db.search(qs[rep], B62, 10, 2)        # eager work between replays
-            assert (single == eager[rep]).all()
-    for q, row in zip(qs, eager):
-        assert (row == _oracle(q, res, offs)).all()
+            assert (single == want[rep]).all()
 
 
 def test_batch_workload_scaled(sw):
@@ -467,6 +506,44 @@ def test_batch_workload_scaled(sw):
     for qi in range(0, len(w.queries), 7):
         want = ocpu.search(w.queries[qi], w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
         assert (got[qi][ids] == want).all(), qi
+
+
+def test_full_size_batched_workload_full_rows(sw):
+    """The full batched workload (the 20 plain queries + 200 of 50..5,000
+    residues, 220 queries x 200,000 sequences) as the benchmark runs it: one
+    batched search planned and captured into a HIP graph, then replayed.
+    Whole rows compared with the oracle: the shortest and the longest query,
+    and both halves of the two pairs of shortest queries (queries are paired
+    two per lane in length order); every other row checked by bounds."""
+    import torch
+    from conftest import workload, oracle_row
+    w = workload("batched")
+    lens = np.diff(w.offsets)
+    qlens = np.array([len(q) for q in w.queries])
+    cat = torch.from_numpy(np.concatenate(w.queries)).cuda()
+    qoffs = np.zeros(len(w.queries) + 1, np.int64)
+    np.cumsum(qlens, out=qoffs[1:])
+    say("full batched workload: %d queries x %d seqs" % (len(w.queries), w.n_seqs))
+    with sw.Database(w.residues, w.offsets) as db:
+        out = torch.full((len(w.queries), db.n_seqs), -1, dtype=torch.int32, device="cuda")
+        db.search_batch_async(cat, qoffs, w.matrix, 10, 2, out)     # plan + capture
+        torch.cuda.synchronize()
+        out.fill_(-1)
+        db.search_batch_async(cat, qoffs, w.matrix, 10, 2, out)     # graph replay
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        del out
+    # the library pairs queries in stable length order, longest first
+    order = sorted(range(len(qlens)), key=lambda q: -qlens[q])
+    pairs = [order[i:i + 2] for i in range(0, len(order), 2)]
+    rows = {order[0], order[-1]} | set(pairs[-1]) | set(pairs[-2])
+    for qi in sorted(rows, key=lambda q: qlens[q]):
+        want = oracle_row(w, w.queries[qi])
+        bad = np.nonzero(got[qi] != want)[0]
+        assert len(bad) == 0, (qi, qlens[qi], bad[:5], got[qi][bad[:5]], want[bad[:5]])
+        say("batched query %d (m=%d): all %d scores equal the oracle" % (qi, qlens[qi], w.n_seqs))
+    for qi, q in enumerate(w.queries):
+        _check_bounds(got[qi], q, lens)
 
 
 def test_autotune_then_searches_stay_exact(sw):
@@ -508,6 +585,12 @@ def test_full_size_long_mix_workload_sampled(sw):
         batch = db.search_batch(w.queries, w.matrix, 10, 2)
     assert (single == batch).all()
     assert diag > 32767 and (single[-1][w.planted] == diag).all()
+    from conftest import oracle_row
     for qi, q in enumerate(w.queries):
-        want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
-        assert (single[qi][ids] == want).all(), qi
+        if qi < 2:     # m = 1,000 and 2,000: every score
+            want = oracle_row(w, q)
+            assert (single[qi] == want).all(), (qi, np.nonzero(single[qi] != want)[0][:5])
+            say("long mix query %d (m=%d): all %d scores equal the oracle" % (qi, len(q), w.n_seqs))
+        else:
+            want = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, ids=ids)
+            assert (single[qi][ids] == want).all(), qi

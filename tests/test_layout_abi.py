@@ -151,3 +151,30 @@ def test_null_handle_calls_fail_cleanly():
     assert L.sw_db_info(None, None, None, None, None) == _native.SW_EINVAL
     L.sw_db_free(None)
     assert b"NULL" in L.sw_last_error()
+
+
+def test_device_argument_checks_reject_bad_buffers():
+    """The binding checks what the C ABI cannot (device buffers' dtype,
+    layout, size and location) before any call: every rejection raises
+    ValueError (here with host tensors, which fail the last check too)."""
+    import torch
+    from paper_2203_11100_amd import _check_search_args, _check_batch_args
+    q = torch.zeros(10, dtype=torch.uint8)
+    out = torch.zeros(100, dtype=torch.int32)
+    cases = [
+        (lambda: _check_search_args(q.to(torch.int32), out, 100), "torch.uint8"),
+        (lambda: _check_search_args(q, out.to(torch.int64), 100), "torch.int32"),
+        (lambda: _check_search_args(q, out[:50], 100), "at least 100"),
+        (lambda: _check_search_args(q, torch.zeros((100, 2), dtype=torch.int32)[:, 0], 100),
+         "contiguous"),
+        (lambda: _check_search_args(q, out, 100), "GPU memory"),
+        (lambda: _check_batch_args(q, np.array([0, 4, 3]), out, 50), "non-decreasing"),
+        (lambda: _check_batch_args(q, np.array([1, 4]), out, 50), "start at 0"),
+        (lambda: _check_batch_args(q, np.array([0, 4, 11]), out, 50), "at least 11"),
+        (lambda: _check_batch_args(q, np.array([0, 4, 10]), out, 51), "at least 102"),
+        (lambda: _check_batch_args(q, np.array([0, 4, 10]), out, 50), "GPU memory"),
+        (lambda: _check_search_args(np.zeros(10, np.uint8), out, 100), "torch tensor"),
+    ]
+    for fn, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            fn()
