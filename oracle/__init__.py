@@ -13,6 +13,11 @@ query a and each database sequence b, the best local alignment score
                          sum S(a_i, b_j) - sum of gap costs),
     gap cost w(k) = o + (k - 1) * e  for a gap of k >= 1 residues.
 
+The end of the best alignment (search tools report where a hit lies) is
+the last matched pair of an optimal chain; of several, the smallest in
+database-then-query order, as 0-based residue indices ((-1, -1) for a
+score of 0): sw_bruteforce_end, sw_gotoh_end and cpu.score_end/search_end.
+
 Three implementations, each written from that definition:
   * sw_bruteforce  - enumerates every chain (tiny inputs only);
   * sw_gotoh       - Gotoh's H/E/F recurrence in plain Python;
@@ -20,6 +25,8 @@ Three implementations, each written from that definition:
                      threaded over database sequences; the timed CPU baseline
                      and the parity source for full-size workloads.
 """
-from .sw_ref import gap_cost, sw_bruteforce, sw_bruteforce_table, sw_gotoh
+from .sw_ref import (gap_cost, sw_bruteforce, sw_bruteforce_end, sw_bruteforce_table, sw_gotoh,
+                     sw_gotoh_end)
 
-__all__ = ["gap_cost", "sw_bruteforce", "sw_bruteforce_table", "sw_gotoh"]
+__all__ = ["gap_cost", "sw_bruteforce", "sw_bruteforce_end", "sw_bruteforce_table", "sw_gotoh",
+           "sw_gotoh_end"]

@@ -106,3 +106,60 @@ def sw_gotoh(a: Sequence[int], b: Sequence[int], S, gap_open: int,
                           E[i][j], F[i][j])
             best = max(best, H[i][j])
     return int(best)
+
+
+def sw_bruteforce_end(a: Sequence[int], b: Sequence[int], S, gap_open: int,
+                      gap_extend: int) -> Tuple[int, int, int]:
+    """Score and end of the best local alignment, by enumeration of all chains.
+
+    The end of a chain is its last matched pair (i_r, j_r).  Several optimal
+    chains may end at different pairs; the end reported is the smallest
+    (j_r, i_r) in database-then-query order over the optimal chains, as
+    0-based residue indices (query, database).  When the score is 0 (no chain
+    scores above 0) the end is (-1, -1).  Exponential: tiny inputs only.
+    """
+    best, end = 0, None
+    for I, J in _chains(len(a), len(b)):
+        s = sum(int(S[a[i]][b[j]]) for i, j in zip(I, J))
+        for t in range(len(I) - 1):
+            s -= gap_cost(I[t + 1] - I[t] - 1, gap_open, gap_extend)
+            s -= gap_cost(J[t + 1] - J[t] - 1, gap_open, gap_extend)
+        if s <= 0:
+            continue
+        key = (J[-1], I[-1])
+        if s > best or (s == best and key < end):
+            best, end = s, key
+    if best == 0:
+        return 0, -1, -1
+    return best, end[1], end[0]
+
+
+def sw_gotoh_end(a: Sequence[int], b: Sequence[int], S, gap_open: int,
+                 gap_extend: int) -> Tuple[int, int, int]:
+    """Gotoh's recurrence (as in sw_gotoh) with the end of the best alignment.
+
+    The end is the cell (i, j) with H(i, j) equal to the score that comes
+    first in database-then-query order (smallest j, then smallest i),
+    returned as 0-based residue indices (i - 1, j - 1); (-1, -1) for a
+    score of 0.  That cell is the last matched pair of an optimal chain, and
+    no optimal chain ends at a smaller (j, i): a cell whose H equals the score
+    through E or F has an earlier cell of the same row or column with at
+    least that H.
+    """
+    m, n = len(a), len(b)
+    NEG = -math.inf
+    H = [[0] * (n + 1) for _ in range(m + 1)]
+    E = [[NEG] * (n + 1) for _ in range(m + 1)]
+    F = [[NEG] * (n + 1) for _ in range(m + 1)]
+    best, end = 0, None
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            E[i][j] = max(E[i][j - 1] - gap_extend, H[i][j - 1] - gap_open)
+            F[i][j] = max(F[i - 1][j] - gap_extend, H[i - 1][j] - gap_open)
+            H[i][j] = max(0, H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]),
+                          E[i][j], F[i][j])
+            if H[i][j] > 0 and (H[i][j] > best or (H[i][j] == best and (j, i) < end)):
+                best, end = H[i][j], (j, i)
+    if best == 0:
+        return 0, -1, -1
+    return int(best), end[1] - 1, end[0] - 1

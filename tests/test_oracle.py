@@ -240,3 +240,91 @@ def test_threaded_search_matches_single_scores():
         assert got[t] == ocpu.score(q, w.seq(int(sid)), w.matrix, 10, 2)
     full = ocpu.search(q, w.residues, w.offsets, w.matrix, 10, 2, threads=3)
     assert (full[ids] == got).all()
+
+
+# ------------------------------------------------------------ alignment ends
+def _tie_heavy_cases(seed, count):
+    """Tiny inputs over 2-3 letters with scores in {-1, 0, 1, 2}: many
+    optimal alignments, so the tie-break decides the end."""
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        k = int(rng.integers(2, 4))
+        a = rng.integers(0, k, int(rng.integers(0, 7))).astype(np.uint8)
+        b = rng.integers(0, k, int(rng.integers(0, 7))).astype(np.uint8)
+        S = rng.integers(-1, 3, size=(k, k)).astype(np.int8)
+        yield a, b, S
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_end_recurrence_equals_definition_bruteforce(seed):
+    """(score, query end, db end): brute force over chains == Gotoh in Python
+    == the C oracle, on tie-heavy and general tiny inputs."""
+    rng = np.random.default_rng(100 + seed)
+    cases = list(_tie_heavy_cases(seed, 30)) + list(_tiny_cases(50 + seed, 15))
+    for a, b, S in cases:
+        for idx in rng.choice(len(GAPS_SMALL), 5, replace=False):
+            o, e = GAPS_SMALL[idx]
+            want = oracle.sw_bruteforce_end(a, b, S, o, e)
+            assert oracle.sw_gotoh_end(a, b, S, o, e) == want, (a, b, S, o, e)
+            assert ocpu.score_end(a, b, S, o, e) == want, (a, b, S, o, e)
+            assert want[0] == oracle.sw_bruteforce(a, b, S, o, e)
+
+
+def test_end_hand_cases():
+    n = 0
+    with open(os.path.join(HERE, "golden", "hand_ends.txt")) as f:
+        for ln in f:
+            if not ln.strip() or ln.startswith("#"):
+                continue
+            q, t, o, e, sc, qe, de = ln.split()
+            a, b = swinputs.encode(q), swinputs.encode(t)
+            want = (int(sc), int(qe), int(de))
+            assert oracle.sw_gotoh_end(a, b, B62, int(o), int(e)) == want, ln
+            assert ocpu.score_end(a, b, B62, int(o), int(e)) == want, ln
+            n += 1
+    assert n >= 5
+
+
+def test_end_embedded_copy_closed_form():
+    """A query copied into a random sequence x q y scores sum S(q_i, q_i)
+    (BLOSUM62's rows peak strictly on the diagonal, so only an exact,
+    ungapped copy reaches it) and ends at the copy's last residue; with two
+    copies the first one's end is reported."""
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        m = int(rng.integers(20, 60))
+        q = swinputs.random_residues(m, rng)
+        x = swinputs.random_residues(int(rng.integers(0, 80)), rng)
+        y = swinputs.random_residues(int(rng.integers(0, 80)), rng)
+        z = swinputs.random_residues(int(rng.integers(0, 30)), rng)
+        diag = int(sum(int(B62[c, c]) for c in q))
+        t1 = np.concatenate([x, q, y])
+        assert ocpu.score_end(q, t1, B62, 10, 2) == (diag, m - 1, len(x) + m - 1)
+        t2 = np.concatenate([x, q, z, q, y])
+        assert ocpu.score_end(q, t2, B62, 10, 2) == (diag, m - 1, len(x) + m - 1)
+        qs = q[:25]
+        assert oracle.sw_gotoh_end(qs, np.concatenate([x[:10], qs, y[:5]]), B62, 10, 2) == \
+            (int(sum(int(B62[c, c]) for c in qs)), len(qs) - 1, min(len(x), 10) + len(qs) - 1)
+
+
+def test_search_end_matches_per_sequence():
+    rng = np.random.default_rng(12)
+    lengths = rng.integers(0, 300, 400)
+    res, offs = swinputs.make_database(lengths, rng)
+    q = swinputs.random_residues(120, rng)
+    sc, qe, de = ocpu.search_end(q, res, offs, B62, 10, 2, threads=4)
+    assert (sc == ocpu.search(q, res, offs, B62, 10, 2)).all()
+    for i in range(0, 400, 13):
+        assert (sc[i], qe[i], de[i]) == ocpu.score_end(q, res[offs[i]:offs[i + 1]], B62, 10, 2)
+    assert ((qe == -1) == (sc == 0)).all() and ((de == -1) == (sc == 0)).all()
+    ids = np.array([5, 3, 399, 0])
+    sub = ocpu.search_end(q, res, offs, B62, 10, 2, ids=ids)
+    for t in range(3):
+        assert (sub[t] == (sc, qe, de)[t][ids]).all()
+
+
+def test_top_hits_order():
+    s = np.array([5, 9, 0, 9, 5, 7, 9, 0])
+    assert ocpu.top_hits(s, 5).tolist() == [1, 3, 6, 5, 0]
+    assert ocpu.top_hits(s, 100).tolist() == [1, 3, 6, 5, 0, 4, 2, 7]
+    assert ocpu.top_hits(s, 0).tolist() == []
