@@ -18,6 +18,12 @@ the last matched pair of an optimal chain; of several, the smallest in
 database-then-query order, as 0-based residue indices ((-1, -1) for a
 score of 0): sw_bruteforce_end, sw_gotoh_end and cpu.score_end/search_end.
 
+Two other alignment modes of the same scoring scheme, global (every
+residue of both sequences aligned, end gaps charged) and semi-global (the
+whole query aligned inside the database sequence, whose overhangs are free),
+are maxima over chains with different end costs and no floor at 0:
+sw_bruteforce_mode, sw_gotoh_mode and cpu.score_mode/search_mode.
+
 Three implementations, each written from that definition:
   * sw_bruteforce  - enumerates every chain (tiny inputs only);
   * sw_gotoh       - Gotoh's H/E/F recurrence in plain Python;
@@ -25,8 +31,10 @@ Three implementations, each written from that definition:
                      threaded over database sequences; the timed CPU baseline
                      and the parity source for full-size workloads.
 """
-from .sw_ref import (gap_cost, sw_bruteforce, sw_bruteforce_end, sw_bruteforce_table, sw_gotoh,
-                     sw_gotoh_end)
+from .sw_ref import (GLOBAL, SEMIGLOBAL, gap_cost, sw_bruteforce, sw_bruteforce_end,
+                     sw_bruteforce_mode, sw_bruteforce_table, sw_gotoh, sw_gotoh_end,
+                     sw_gotoh_mode)
 
-__all__ = ["gap_cost", "sw_bruteforce", "sw_bruteforce_end", "sw_bruteforce_table", "sw_gotoh",
-           "sw_gotoh_end"]
+__all__ = ["GLOBAL", "SEMIGLOBAL", "gap_cost", "sw_bruteforce", "sw_bruteforce_end",
+           "sw_bruteforce_mode", "sw_bruteforce_table", "sw_gotoh", "sw_gotoh_end",
+           "sw_gotoh_mode"]

@@ -26,6 +26,11 @@ def _load():
         lib.swo_search.restype = ctypes.c_int
         lib.swo_search.argtypes = [P, I64, P, P, P, I64, P, ctypes.c_int32, I64, I64, P,
                                    ctypes.c_int32]
+        lib.swo_score_mode.restype = I64
+        lib.swo_score_mode.argtypes = [P, I64, P, I64, P, ctypes.c_int32, I64, I64, ctypes.c_int32]
+        lib.swo_search_mode.restype = ctypes.c_int
+        lib.swo_search_mode.argtypes = [P, I64, P, P, P, I64, P, ctypes.c_int32, I64, I64,
+                                        ctypes.c_int32, P, ctypes.c_int32]
         lib.swo_score_end.restype = I64
         lib.swo_score_end.argtypes = [P, I64, P, I64, P, ctypes.c_int32, I64, I64, P, P]
         lib.swo_search_end.restype = ctypes.c_int
@@ -131,3 +136,43 @@ def top_hits(scores, k: int):
     k = min(int(k), len(scores))
     order = np.lexsort((np.arange(len(scores)), -scores.astype(np.int64)))
     return order[:k]
+
+
+_MODES = {"global": 1, "semiglobal": 2}
+
+
+def score_mode(a, b, S, gap_open: int, gap_extend: int, mode: str) -> int:
+    """Global or semi-global score (see sw_ref.sw_gotoh_mode)."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.uint8)
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    r = _load().swo_score_mode(_ptr(a), len(a), _ptr(b), len(b), _ptr(S), S.shape[0], gap_open,
+                               gap_extend, _MODES[mode])
+    if r == np.iinfo(np.int64).min:
+        raise MemoryError("oracle allocation failed")
+    return int(r)
+
+
+def search_mode(query, residues, offsets, S, gap_open: int, gap_extend: int, mode: str,
+                ids: Optional[np.ndarray] = None, threads: Optional[int] = None) -> np.ndarray:
+    """Global or semi-global scores of `query` against every database
+    sequence (or the subset `ids`)."""
+    q = np.ascontiguousarray(query, dtype=np.uint8)
+    res = np.ascontiguousarray(residues, dtype=np.uint8)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    S = np.ascontiguousarray(S, dtype=np.int8)
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n_items = len(ids)
+    else:
+        n_items = len(offs) - 1
+    out = np.zeros(n_items, dtype=np.int64)
+    if n_items == 0:
+        return out
+    rc = _load().swo_search_mode(_ptr(q), len(q), _ptr(res), _ptr(offs),
+                                 _ptr(ids) if ids is not None else None, n_items, _ptr(S),
+                                 S.shape[0], gap_open, gap_extend, _MODES[mode], _ptr(out),
+                                 threads or default_threads())
+    if rc != 0:
+        raise RuntimeError("oracle search failed")
+    return out

@@ -95,6 +95,50 @@ int64_t swo_score_end(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n,
   return best;
 }
 
+/* Global (mode 1) and semi-global (mode 2) scores: Gotoh's recurrence
+ * without the 0 in H's maximum, with borders H(i, 0) = -w(i) (the query's
+ * leading residues), H(0, j) = -w(j) (global) or 0 (semi-global: free
+ * leading database residues) and E(i, 0) = F(0, j) = -infinity; the score
+ * is H(m, n) (global) or max_j H(m, j) (semi-global: free trailing database
+ * residues), H(m, 0) when n = 0.  w(k) = o + (k - 1) e, w(0) = 0.  Returns
+ * INT64_MIN on allocation failure. */
+static int64_t gapw(int64_t k, int64_t o, int64_t e) { return k == 0 ? 0 : o + (k - 1) * e; }
+
+int64_t swo_score_mode(const uint8_t* a, int64_t m, const uint8_t* b, int64_t n,
+                       const int8_t* S, int32_t k, int64_t o, int64_t e, int32_t mode) {
+  if (n == 0) return -gapw(m, o, e);
+  int64_t* Hrow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  int64_t* Frow = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n + 1));
+  if (!Hrow || !Frow) { free(Hrow); free(Frow); return INT64_MIN; }
+  for (int64_t j = 0; j <= n; ++j) {   /* row 0 */
+    Hrow[j] = mode == 1 ? -gapw(j, o, e) : 0;
+    Frow[j] = NEG_INF;
+  }
+  for (int64_t i = 1; i <= m; ++i) {
+    const int8_t* Srow = S + (size_t)a[i - 1] * (size_t)k;
+    int64_t h_diag = Hrow[0];         /* H(i-1, 0) */
+    int64_t h_left = -gapw(i, o, e);  /* H(i, 0) */
+    int64_t E = NEG_INF;              /* E(i, 0) */
+    Hrow[0] = h_left;
+    for (int64_t j = 1; j <= n; ++j) {
+      E = max2(E - e, h_left - o);
+      Frow[j] = max2(Frow[j] - e, Hrow[j] - o);
+      int64_t h = h_diag + Srow[b[j - 1]];
+      h = max2(h, E);
+      h = max2(h, Frow[j]);
+      h_diag = Hrow[j];
+      Hrow[j] = h;
+      h_left = h;
+    }
+  }
+  int64_t score = Hrow[n];
+  if (mode != 1)
+    for (int64_t j = 1; j <= n; ++j) score = max2(score, Hrow[j]);
+  free(Hrow);
+  free(Frow);
+  return score;
+}
+
 typedef struct {
   const uint8_t* q; int64_t m;
   const uint8_t* res; const int64_t* offs;
@@ -103,6 +147,7 @@ typedef struct {
   int64_t* out;
   int64_t* qend;             /* with dend: ends wanted (swo_search_end) */
   int64_t* dend;
+  int32_t mode;              /* 0 local, 1 global, 2 semi-global */
   int64_t next;
   int failed;
   pthread_mutex_t lock;
@@ -120,10 +165,16 @@ static void* worker(void* arg) {
     for (; it < end; ++it) {
       int64_t sid = J->ids ? J->ids[it] : it;
       int64_t b0 = J->offs[sid], n = J->offs[sid + 1] - b0;
-      int64_t s = J->qend ? swo_score_end(J->q, J->m, J->res + b0, n, J->S, J->k, J->o, J->e,
-                                          &J->qend[it], &J->dend[it])
-                          : swo_score(J->q, J->m, J->res + b0, n, J->S, J->k, J->o, J->e);
-      if (s < 0) J->failed = 1;
+      int64_t s;
+      if (J->mode) {
+        s = swo_score_mode(J->q, J->m, J->res + b0, n, J->S, J->k, J->o, J->e, J->mode);
+        if (s == INT64_MIN) J->failed = 1;
+      } else {
+        s = J->qend ? swo_score_end(J->q, J->m, J->res + b0, n, J->S, J->k, J->o, J->e,
+                                    &J->qend[it], &J->dend[it])
+                    : swo_score(J->q, J->m, J->res + b0, n, J->S, J->k, J->o, J->e);
+        if (s < 0) J->failed = 1;
+      }
       J->out[it] = s;
     }
   }
@@ -138,7 +189,17 @@ static int run_search(job_t* Jp, int32_t n_threads);
 int swo_search(const uint8_t* q, int64_t m, const uint8_t* res, const int64_t* offs,
                const int64_t* ids, int64_t n_items, const int8_t* S, int32_t k,
                int64_t o, int64_t e, int64_t* out, int32_t n_threads) {
-  job_t J = {q, m, res, offs, ids, n_items, S, k, o, e, out, NULL, NULL, 0, 0,
+  job_t J = {q, m, res, offs, ids, n_items, S, k, o, e, out, NULL, NULL, 0, 0, 0,
+             PTHREAD_MUTEX_INITIALIZER};
+  return run_search(&J, n_threads);
+}
+
+/* swo_search for the global (mode 1) or semi-global (mode 2) score. */
+int swo_search_mode(const uint8_t* q, int64_t m, const uint8_t* res, const int64_t* offs,
+                    const int64_t* ids, int64_t n_items, const int8_t* S, int32_t k, int64_t o,
+                    int64_t e, int32_t mode, int64_t* out, int32_t n_threads) {
+  if (mode != 1 && mode != 2) return -1;
+  job_t J = {q, m, res, offs, ids, n_items, S, k, o, e, out, NULL, NULL, mode, 0, 0,
              PTHREAD_MUTEX_INITIALIZER};
   return run_search(&J, n_threads);
 }
@@ -149,7 +210,7 @@ int swo_search_end(const uint8_t* q, int64_t m, const uint8_t* res, const int64_
                    const int64_t* ids, int64_t n_items, const int8_t* S, int32_t k,
                    int64_t o, int64_t e, int64_t* out, int64_t* qend, int64_t* dend,
                    int32_t n_threads) {
-  job_t J = {q, m, res, offs, ids, n_items, S, k, o, e, out, qend, dend, 0, 0,
+  job_t J = {q, m, res, offs, ids, n_items, S, k, o, e, out, qend, dend, 0, 0, 0,
              PTHREAD_MUTEX_INITIALIZER};
   return run_search(&J, n_threads);
 }

@@ -163,3 +163,83 @@ def sw_gotoh_end(a: Sequence[int], b: Sequence[int], S, gap_open: int,
     if best == 0:
         return 0, -1, -1
     return int(best), end[1] - 1, end[0] - 1
+
+
+# ------------------------------------------------------- global, semi-global
+# Other alignment modes of the same scoring scheme (SW# also offers global
+# and semi-global alignment).  Both are maxima over chains of matched pairs
+# with the same inner gap costs as the local score; they differ in what the
+# residues before the first and after the last matched pair cost:
+#   global      : every residue of both sequences is aligned, so the leading
+#                 residues of each sequence form one gap each (w(i_1 - 1) and
+#                 w(j_1 - 1)), the trailing ones too; the empty chain costs
+#                 w(m) + w(n);
+#   semi-global : the whole query is aligned within the database sequence:
+#                 the query's leading and trailing residues form one gap each,
+#                 the database sequence's overhangs are free; the empty chain
+#                 costs w(m).
+# There is no floor at 0: scores may be negative.
+GLOBAL, SEMIGLOBAL = "global", "semiglobal"
+
+
+def sw_bruteforce_mode(a: Sequence[int], b: Sequence[int], S, gap_open: int, gap_extend: int,
+                       mode: str) -> int:
+    """Global or semi-global score by enumeration of all chains (tiny inputs)."""
+    if mode not in (GLOBAL, SEMIGLOBAL):
+        raise ValueError(mode)
+    m, n = len(a), len(b)
+
+    def ends(first_i, first_j, last_i, last_j):
+        # costs of the unmatched residues before the first and after the
+        # last matched pair (0-based indices; -1 / m, n for the empty chain)
+        c = gap_cost(first_i, gap_open, gap_extend) + gap_cost(m - 1 - last_i, gap_open, gap_extend)
+        if mode == GLOBAL:
+            c += gap_cost(first_j, gap_open, gap_extend) + gap_cost(n - 1 - last_j, gap_open,
+                                                                     gap_extend)
+        return c
+
+    if mode == GLOBAL:
+        best = -(gap_cost(m, gap_open, gap_extend) + gap_cost(n, gap_open, gap_extend))
+    else:
+        best = -gap_cost(m, gap_open, gap_extend)
+    for I, J in _chains(m, n):
+        s = sum(int(S[a[i]][b[j]]) for i, j in zip(I, J))
+        for t in range(len(I) - 1):
+            s -= gap_cost(I[t + 1] - I[t] - 1, gap_open, gap_extend)
+            s -= gap_cost(J[t + 1] - J[t] - 1, gap_open, gap_extend)
+        s -= ends(I[0], J[0], I[-1], J[-1])
+        best = max(best, s)
+    return best
+
+
+def sw_gotoh_mode(a: Sequence[int], b: Sequence[int], S, gap_open: int, gap_extend: int,
+                  mode: str) -> int:
+    """Gotoh's recurrence for the global and semi-global scores.
+
+    As in sw_gotoh but without the 0 in H's maximum, and with borders that
+    charge what the mode charges: H(i, 0) = -w(i) (the query's leading
+    residues); H(0, j) = -w(j) in global mode, 0 in semi-global mode (free
+    leading database residues); E(i, 0) = F(0, j) = -infinity.  The score is
+    H(m, n) (global) or max_j H(m, j) (semi-global: free trailing database
+    residues); for n = 0 it is H(m, 0).
+    """
+    if mode not in (GLOBAL, SEMIGLOBAL):
+        raise ValueError(mode)
+    m, n = len(a), len(b)
+    NEG = -math.inf
+    w = lambda k: gap_cost(k, gap_open, gap_extend)
+    H = [[0] * (n + 1) for _ in range(m + 1)]
+    E = [[NEG] * (n + 1) for _ in range(m + 1)]
+    F = [[NEG] * (n + 1) for _ in range(m + 1)]
+    for i in range(1, m + 1):
+        H[i][0] = -w(i)
+    for j in range(1, n + 1):
+        H[0][j] = -w(j) if mode == GLOBAL else 0
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            E[i][j] = max(E[i][j - 1] - gap_extend, H[i][j - 1] - gap_open)
+            F[i][j] = max(F[i - 1][j] - gap_extend, H[i - 1][j] - gap_open)
+            H[i][j] = max(H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]), E[i][j], F[i][j])
+    if mode == GLOBAL or n == 0:
+        return int(H[m][n])
+    return int(max(H[m][j] for j in range(1, n + 1)))

@@ -328,3 +328,92 @@ def test_top_hits_order():
     assert ocpu.top_hits(s, 5).tolist() == [1, 3, 6, 5, 0]
     assert ocpu.top_hits(s, 100).tolist() == [1, 3, 6, 5, 0, 4, 2, 7]
     assert ocpu.top_hits(s, 0).tolist() == []
+
+
+# ------------------------------------------------- global and semi-global modes
+MODES = (oracle.GLOBAL, oracle.SEMIGLOBAL)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_modes_recurrence_equals_definition_bruteforce(seed):
+    """Global and semi-global: chain enumeration == Gotoh in Python == C."""
+    rng = np.random.default_rng(200 + seed)
+    for a, b, S in list(_tiny_cases(300 + seed, 25)) + list(_tie_heavy_cases(400 + seed, 10)):
+        for idx in rng.choice(len(GAPS_SMALL), 5, replace=False):
+            o, e = GAPS_SMALL[idx]
+            for mode in MODES:
+                want = oracle.sw_bruteforce_mode(a, b, S, o, e, mode)
+                assert oracle.sw_gotoh_mode(a, b, S, o, e, mode) == want, (a, b, S, o, e, mode)
+                assert ocpu.score_mode(a, b, S, o, e, mode) == want, (a, b, S, o, e, mode)
+
+
+def _nw_linear(a, b, S, g):
+    """Needleman-Wunsch with linear gap cost g per residue (one matrix)."""
+    m, n = len(a), len(b)
+    H = np.zeros((m + 1, n + 1), dtype=np.int64)
+    H[:, 0] = -g * np.arange(m + 1)
+    H[0, :] = -g * np.arange(n + 1)
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            H[i, j] = max(H[i - 1, j - 1] + int(S[a[i - 1]][b[j - 1]]), H[i - 1, j] - g,
+                          H[i, j - 1] - g)
+    return int(H[m, n])
+
+
+def test_global_linear_gaps_is_needleman_wunsch():
+    rng = np.random.default_rng(21)
+    for _ in range(40):
+        a = swinputs.random_residues(int(rng.integers(0, 30)), rng)
+        b = swinputs.random_residues(int(rng.integers(0, 30)), rng)
+        g = int(rng.integers(0, 12))
+        assert ocpu.score_mode(a, b, B62, g, g, "global") == _nw_linear(a, b, B62, g)
+
+
+def test_modes_closed_forms():
+    """BLOSUM62 rows peak strictly on the diagonal, so: a sequence against
+    itself scores sum S(q_i, q_i) globally; against a prefix of itself
+    missing k residues, that prefix's sum minus one gap w(k) (global and
+    semi-global); a query copied into flanks scores its diagonal sum
+    semi-globally; an empty database sequence costs w(m)."""
+    rng = np.random.default_rng(22)
+    w = lambda k: 0 if k == 0 else 10 + 2 * (k - 1)
+    for _ in range(25):
+        m = int(rng.integers(1, 80))
+        q = swinputs.random_residues(m, rng)
+        diag = lambda s: int(sum(int(B62[c, c]) for c in s))
+        assert ocpu.score_mode(q, q, B62, 10, 2, "global") == diag(q)
+        k = int(rng.integers(0, m))
+        for mode in MODES:
+            assert ocpu.score_mode(q, q[:m - k], B62, 10, 2, mode) == diag(q[:m - k]) - w(k)
+            assert ocpu.score_mode(q, np.zeros(0, np.uint8), B62, 10, 2, mode) == -w(m)
+        x = swinputs.random_residues(int(rng.integers(0, 50)), rng)
+        y = swinputs.random_residues(int(rng.integers(0, 50)), rng)
+        assert ocpu.score_mode(q, np.concatenate([x, q, y]), B62, 10, 2, "semiglobal") == diag(q)
+    assert ocpu.score_mode(np.zeros(0, np.uint8), q, B62, 10, 2, "semiglobal") == 0
+    assert ocpu.score_mode(np.zeros(0, np.uint8), q, B62, 10, 2, "global") == -w(len(q))
+
+
+def test_modes_invariants():
+    """Swap symmetry (global, symmetric matrix), reversal invariance (both),
+    and local >= semi-global >= global for the same inputs."""
+    rng = np.random.default_rng(23)
+    for _ in range(40):
+        a = swinputs.random_residues(int(rng.integers(0, 60)), rng)
+        b = swinputs.random_residues(int(rng.integers(0, 60)), rng)
+        o = int(rng.integers(0, 14)); e = int(rng.integers(0, o + 1))
+        g = ocpu.score_mode(a, b, B62, o, e, "global")
+        s = ocpu.score_mode(a, b, B62, o, e, "semiglobal")
+        assert g == ocpu.score_mode(b, a, B62, o, e, "global")
+        assert g == ocpu.score_mode(a[::-1], b[::-1], B62, o, e, "global")
+        assert s == ocpu.score_mode(a[::-1], b[::-1], B62, o, e, "semiglobal")
+        assert ocpu.score(a, b, B62, o, e) >= s >= g
+
+
+def test_search_mode_matches_per_sequence():
+    rng = np.random.default_rng(24)
+    res, offs = swinputs.make_database(rng.integers(0, 200, 300), rng)
+    q = swinputs.random_residues(90, rng)
+    for mode in MODES:
+        got = ocpu.search_mode(q, res, offs, B62, 10, 2, mode, threads=4)
+        for i in range(0, 300, 11):
+            assert got[i] == ocpu.score_mode(q, res[offs[i]:offs[i + 1]], B62, 10, 2, mode)
