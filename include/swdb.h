@@ -158,6 +158,102 @@ int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* qu
                           int32_t n_queries, const int8_t* matrix, int32_t gap_open,
                           int32_t gap_extend, int32_t* d_out_scores, void* hip_stream);
 
+/* ------------------------------------------------------------------ top hits
+ * sw_search_topk: one search (as sw_search) followed by its k best hits with
+ * the end of each hit's best local alignment.  A search tool reports the
+ * best-scoring database sequences and their alignments, not only one value
+ * per sequence (paper section 2.3, SW# "computes biological sequence
+ * alignments"); the end cell is where the traceback of that alignment would
+ * start.
+ *   k          : 0 <= k <= SW_MAX_TOPK (SW_ERANGE above); min(k, n_seqs) hits
+ *                are returned.
+ *   out_scores : host, int32_t[n_seqs] (every score, as sw_search), or NULL.
+ *   out_hits   : host, sw_hit[min(k, n_seqs)], best first: higher score
+ *                first, equal scores by smaller sequence index.
+ * A hit's end is the cell (query_end, db_end) holding its score that comes
+ * first in database-then-query order (the smallest database position, then
+ * the smallest query position), as 0-based residue indices; a score of 0
+ * (no aligned pair scores above 0) has no end and reports (-1, -1).  The
+ * selection runs on the device over the exact scores; the ends come from an
+ * exact 32-bit pass over the k hit sequences only, so the search itself
+ * costs the same as sw_search. */
+#define SW_MAX_TOPK 4096
+typedef struct sw_hit {
+  int32_t seq;        /* database sequence index (original order) */
+  int32_t score;      /* its score */
+  int32_t query_end;  /* query position of the alignment's last pair, or -1 */
+  int32_t db_end;     /* database-sequence position of that pair, or -1 */
+} sw_hit;
+int sw_search_topk(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* out_scores,
+                   sw_hit* out_hits);
+/* sw_search_topk_async: device query, score row and hit list (the score row
+ * is required here: d_out_scores int32_t[n_seqs], d_hits sw_hit[min(k,
+ * n_seqs)]), enqueued on hip_stream like sw_search_async. */
+int sw_search_topk_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
+                         const int8_t* matrix, int32_t gap_open, int32_t gap_extend, int32_t k,
+                         int32_t* d_out_scores, sw_hit* d_hits, void* hip_stream);
+
+/* ---------------------------------------------------------- hybrid search
+ * sw_search_hybrid: one query against every database sequence with host
+ * cores and the GPU at once (paper section 2.3: SW#db uses CPUs and GPUs
+ * simultaneously with dynamic work distribution; the experiments of section
+ * 4.1 give the CPU side one thread, T=1).  The short bins form one shared
+ * work order, longest first: the calling thread launches the GPU's
+ * inter-task kernel on chunks taken from the front (at most two chunks
+ * queued, the next claimed when the earlier one ends), while `cpu_threads`
+ * host threads (0: one fewer than the host's hardware threads) take single
+ * bins from the back and score them with the host scorer (Farrar's striped
+ * 16-bit SIMD recurrence with exact 32-bit rescoring, the code behind
+ * sw_host_search); the two meet where their speeds balance.  Long sequences
+ * and the GPU's rescoring stay on the GPU.  Scores are identical to
+ * sw_search.  Host buffers, synchronous; `stats` may be NULL. */
+typedef struct sw_hybrid_stats {
+  int64_t gpu_bins, cpu_bins;      /* short bins scored by each side */
+  int64_t gpu_cells, cpu_cells;    /* cells (query length x residues) of each side */
+  int32_t cpu_threads;             /* host threads used */
+  float ms;                        /* wall time of the call */
+} sw_hybrid_stats;
+int sw_search_hybrid(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, int32_t cpu_threads,
+                     int32_t* out_scores, sw_hybrid_stats* stats);
+
+/* sw_host_search: the host scorer of the hybrid search on its own, over
+ * host buffers laid out as for sw_db_load: every sequence's score against
+ * the query, computed by `threads` host threads (0: all hardware threads).
+ * It needs no GPU; the GPU entry points never call it. */
+int sw_host_search(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+                   const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t threads, int32_t* out_scores);
+
+/* ------------------------------------------------------------ other modes
+ * sw_search_mode: one query against every database sequence with another
+ * alignment operation of the same scoring scheme (paper section 2.3: SW#
+ * aligns in several modes; section 5 names other alignment operations as
+ * future work).  Every mode is a maximum over chains of matched pairs with
+ * the local score's inner gap costs and no floor at 0:
+ *   SW_MODE_LOCAL      : the local score (exactly sw_search);
+ *   SW_MODE_GLOBAL     : the leading and trailing unmatched residues of each
+ *                        sequence also form one gap each (Needleman-Wunsch
+ *                        with affine gaps; an empty sequence scores
+ *                        -w(query_len), w(k) = gap_open + (k-1) gap_extend,
+ *                        w(0) = 0);
+ *   SW_MODE_SEMIGLOBAL : the query is aligned end to end, the database
+ *                        sequence's leading and trailing residues are free
+ *                        (the query's best placement inside each sequence).
+ * Scores are exact 32-bit integers and may be negative.  Calls whose scores
+ * could leave +-2^28 - gap_open + (gap_extend + 128) x (query_len + 512 +
+ * longest sequence + 1024) > 2^28 - return SW_ERANGE.  Sequences shorter
+ * than the long threshold run in the int32 inter-task kernel (one sequence
+ * per lane), longer ones in the int32 intra-task wavefront kernel.  Buffers
+ * as sw_search / sw_search_async. */
+enum sw_mode { SW_MODE_LOCAL = 0, SW_MODE_GLOBAL = 1, SW_MODE_SEMIGLOBAL = 2 };
+int sw_search_mode(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t mode, int32_t* out_scores);
+int sw_search_mode_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
+                         const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                         int32_t mode, int32_t* d_out_scores, void* hip_stream);
+
 /* Description of the most recent failure on this thread ("" if none).  The
  * string stays valid until the next call on the same thread. */
 const char* sw_last_error(void);

@@ -15,11 +15,22 @@ import numpy as np
 from . import _native
 from ._native import (SwError, SW_ALPHA, SW_BIN_SEQS, SW_PAD_CODE, SW_MIN_BIN_LEN,
                       SW_DEFAULT_LONG_THRESHOLD, SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS,
-                      SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES, SW_OPT_GRAPHS)
+                      SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES, SW_OPT_GRAPHS,
+                      SW_MAX_TOPK, SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL)
 
-__all__ = ["Database", "Context", "SwError", "plan", "pack", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
+__all__ = ["Database", "Context", "SwError", "plan", "pack", "host_search", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
            "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
-           "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS"]
+           "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS",
+           "SW_MAX_TOPK", "HIT_DTYPE", "SW_MODE_LOCAL", "SW_MODE_GLOBAL", "SW_MODE_SEMIGLOBAL",
+           "MODES"]
+
+# alignment operation names accepted by Database.search_mode
+MODES = {"local": SW_MODE_LOCAL, "global": SW_MODE_GLOBAL, "semiglobal": SW_MODE_SEMIGLOBAL}
+
+# one sw_hit: database sequence, score, query end, database end (0-based; -1
+# when the score is 0)
+HIT_DTYPE = np.dtype([("seq", np.int32), ("score", np.int32), ("query_end", np.int32),
+                      ("db_end", np.int32)])
 
 
 def _ptr(a) -> Optional[int]:
@@ -116,6 +127,19 @@ def pack(residues, offsets, long_threshold: int = 0) -> dict:
             "long_ids": long_ids[:info["n_long"]]}
 
 
+def host_search(residues, offsets, query, matrix, gap_open: int = 10, gap_extend: int = 2,
+                threads: int = 0) -> np.ndarray:
+    """Scores with the hybrid search's host scorer alone (sw_host_search):
+    host buffers, host threads, no GPU."""
+    res, offs, q = _u8(residues), _i64(offsets), _u8(query)
+    m = _matrix(matrix)
+    out = np.empty(len(offs) - 1, dtype=np.int32)
+    _native.check(_native.lib().sw_host_search(_ptr(res), _ptr(offs), len(offs) - 1, _ptr(q),
+                                               len(q), _ptr(m), gap_open, gap_extend,
+                                               int(threads), _ptr(out)))
+    return out
+
+
 class Database:
     """A protein database resident in device memory (sw_db_load)."""
 
@@ -195,6 +219,66 @@ class Database:
         m = _matrix(matrix)
         _native.check(_native.lib().sw_search_async(
             self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
+            _ptr(d_out), _stream_handle(stream)))
+
+    def search_topk(self, query, matrix, gap_open: int = 10, gap_extend: int = 2, k: int = 10,
+                    scores: bool = False):
+        """The k best hits of one query (sw_search_topk): a structured array
+        of HIT_DTYPE, best first, with the end of each hit's best alignment;
+        with scores=True also every score (a second return value)."""
+        q = _u8(query)
+        m = _matrix(matrix)
+        kk = max(0, min(int(k), self.n_seqs))
+        hits = np.zeros(kk, dtype=HIT_DTYPE)
+        out = np.empty(self.n_seqs, dtype=np.int32) if scores else None
+        _native.check(_native.lib().sw_search_topk(self._h, _ptr(q), len(q), _ptr(m), gap_open,
+                                                   gap_extend, int(k), _ptr(out), _ptr(hits)))
+        return (hits, out) if scores else hits
+
+    def search_topk_async(self, d_query, matrix, gap_open: int, gap_extend: int, k: int, d_out,
+                          d_hits, stream=None):
+        """Device buffers (torch tensors): d_query uint8[m], d_out int32[n_seqs],
+        d_hits int32[min(k, n_seqs), 4] (rows of seq, score, query end, db end)."""
+        _check_search_args(d_query, d_out, self.n_seqs)
+        _check_tensor(d_hits, "d_hits", "int32", 4 * max(0, min(int(k), self.n_seqs)))
+        _check_on_gpu(d_hits=d_hits)
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_search_topk_async(
+            self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend, int(k),
+            _ptr(d_out), _ptr(d_hits), _stream_handle(stream)))
+
+    def search_hybrid(self, query, matrix, gap_open: int = 10, gap_extend: int = 2,
+                      cpu_threads: int = 0):
+        """One query with host cores and the GPU at once (sw_search_hybrid):
+        returns (scores, stats)."""
+        q = _u8(query)
+        m = _matrix(matrix)
+        out = np.empty(self.n_seqs, dtype=np.int32)
+        st = _native.HybridStats()
+        _native.check(_native.lib().sw_search_hybrid(self._h, _ptr(q), len(q), _ptr(m), gap_open,
+                                                     gap_extend, int(cpu_threads), _ptr(out),
+                                                     ctypes.byref(st)))
+        return out, {k: getattr(st, k) for k, _ in _native.HybridStats._fields_}
+
+    def search_mode(self, query, matrix, gap_open: int = 10, gap_extend: int = 2,
+                    mode="global") -> np.ndarray:
+        """Scores of one query in another alignment mode (sw_search_mode):
+        "local", "global" or "semiglobal" (or an SW_MODE_* value)."""
+        q = _u8(query)
+        m = _matrix(matrix)
+        md = MODES[mode] if isinstance(mode, str) else int(mode)
+        out = np.empty(self.n_seqs, dtype=np.int32)
+        _native.check(_native.lib().sw_search_mode(self._h, _ptr(q), len(q), _ptr(m), gap_open,
+                                                   gap_extend, md, _ptr(out)))
+        return out
+
+    def search_mode_async(self, d_query, matrix, gap_open: int, gap_extend: int, mode, d_out,
+                          stream=None):
+        _check_search_args(d_query, d_out, self.n_seqs)
+        m = _matrix(matrix)
+        md = MODES[mode] if isinstance(mode, str) else int(mode)
+        _native.check(_native.lib().sw_search_mode_async(
+            self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend, md,
             _ptr(d_out), _stream_handle(stream)))
 
     def search_batch(self, queries: Sequence, matrix, gap_open: int = 10,

@@ -22,6 +22,8 @@ SW_DEFAULT_LONG_THRESHOLD = 2048
 SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 1, 2, 3, 4, 5
 SW_OPT_INTRA_WAVES = 6
 SW_OPT_GRAPHS = 7
+SW_MAX_TOPK = 4096
+SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1, 2
 
 _STATUS_NAMES = {1: "SW_EINVAL", 2: "SW_ERANGE", 3: "SW_ENOMEM", 4: "SW_EDEVICE", 5: "SW_EBUSY"}
 
@@ -49,6 +51,12 @@ class Stats(ctypes.Structure):
                 ("rows", ctypes.c_int32), ("waves", ctypes.c_int32)]
 
 
+class HybridStats(ctypes.Structure):
+    _fields_ = [("gpu_bins", ctypes.c_int64), ("cpu_bins", ctypes.c_int64),
+                ("gpu_cells", ctypes.c_int64), ("cpu_cells", ctypes.c_int64),
+                ("cpu_threads", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+
 TUNE_BUCKETS, TUNE_CANDIDATES = 4, 4
 
 
@@ -72,6 +80,13 @@ SIGNATURES = {
     "sw_db_info": (ctypes.c_int, [P, P, P, P, P]),
     "sw_search": (ctypes.c_int, [P, P, I32, P, I32, I32, P]),
     "sw_search_async": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
+    "sw_search_topk": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P]),
+    "sw_search_topk_async": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P, P]),
+    "sw_search_hybrid": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P,
+                                        ctypes.POINTER(HybridStats)]),
+    "sw_host_search": (ctypes.c_int, [P, P, I64, P, I32, P, I32, I32, I32, P]),
+    "sw_search_mode": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P]),
+    "sw_search_mode_async": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P]),
     "sw_search_batch": (ctypes.c_int, [P, P, P, I32, P, I32, I32, P]),
     "sw_search_batch_async": (ctypes.c_int, [P, P, P, I32, P, I32, I32, P, P]),
     "sw_last_error": (ctypes.c_char_p, []),

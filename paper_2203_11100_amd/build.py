@@ -9,7 +9,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswdb.so")
-SOURCES = ["layout.cpp", "runtime.hip", "k_inter.hip", "k_batch.hip", "k_intra.hip", "k_misc.hip"]
+SOURCES = ["layout.cpp", "runtime.hip", "k_inter.hip", "k_batch.hip", "k_intra.hip", "k_misc.hip", "k_hits.hip", "k_modes.hip",
+           "cpu_scorer.cpp"]
+HOST_SOURCES = ("cpu_scorer.cpp",)
 ARCH = os.environ.get("SWDB_OFFLOAD_ARCH", "gfx950")
 
 
@@ -25,10 +27,14 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(HERE, "_build", src.replace(".", "_") + ".o")
-        cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-Wall", "-Wno-unused-function", "-x", "hip",
-               "-c", os.path.join(CSRC, src), "-o", obj]
+        if src in HOST_SOURCES:      # host-only C++ (no device code)
+            cmd = [hipcc(), "-x", "c++", "-O3", "-std=c++17", "-fPIC", "-Wall",
+                   "-c", os.path.join(CSRC, src), "-o", obj]
+        else:
+            cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+                   "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                   "-Wall", "-Wno-unused-function", "-x", "hip",
+                   "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))
@@ -44,7 +50,8 @@ def build(verbose: bool = True, jobs: int = 8) -> str:
             print("compile failed: %s" % src, file=sys.stderr)
     if failed:
         raise RuntimeError("libswdb build failed")
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-pthread", "-o",
+           LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -97,6 +97,27 @@ struct IntraArgs {
   int2* scratch;              // per-workgroup boundary rows
   int64_t scratch_stride;     // int2 elements per workgroup
   int32_t* out;
+  int4* ends;                 // non-null: {sid, score, query end, db end} per item
+                              // (end coordinates, instead of scores to `out`)
+  int32_t mode;               // SW_MODE_*: local (with or without ends), global,
+                              // semi-global (single query q0)
+  int32_t m;                  // query length (global and semi-global)
+};
+
+// Global / semi-global inter-task kernel (k_modes.hip): one database
+// sequence per lane, strips of R query rows, int32.
+struct ModeArgs {
+  const uint32_t* res;        // interleaved store (dwords)
+  const BinDesc* bins;
+  const int32_t* slot_seq;
+  const int64_t* offs;
+  int32_t n_halfbins;         // 2 x short bins: one wave per half bin
+  int32_t n_strips;
+  int32_t m;
+  int32_t go, ge;
+  const int32_t* prof;        // [n_strips][26][R] int32
+  int2* rb;                   // boundary rows: 4 x res_off + j * 128 + slot
+  int32_t* out;
 };
 
 // Packed intra-task kernel for the long list of a single search: the two
@@ -151,6 +172,22 @@ struct BatchArgs {
   int32_t sat_limit;
 };
 
+// Device state of the top-k selection (k_hits.hip): the radix histogram,
+// the key digits fixed so far, how many keys equal to the prefix are still
+// needed, the pass's finished-workgroup ticket, the count of keys above the
+// final threshold collected so far, and per-workgroup counts of keys equal
+// to the threshold.
+constexpr int kTopkMaxBlocks = 512;
+struct TopkState {
+  uint32_t hist[256];
+  uint32_t prefix;
+  int32_t need;
+  uint32_t done;
+  int32_t n_gt;
+  int32_t blockcnt[kTopkMaxBlocks];
+};
+static_assert(sizeof(TopkState) % 8 == 0, "TopkState keeps the arrays after it 8-byte aligned");
+
 // Kernel launchers (return hipSuccess or the launch error).
 hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint32_t* prof,
                           int m_pad, int R, int8_t* prof2, uint32_t* prof3, int m_pad2,
@@ -162,6 +199,19 @@ hipError_t launch_intra(int RR, int W2, int grid, const IntraArgs& a, hipStream_
 hipError_t launch_intra_pairs(int R, int W2, int grid, const IntraPairArgs& a, hipStream_t s);
 hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t s);
 int batch_workgroups_per_cu(int R, int W);
+hipError_t launch_mode_profile(const uint8_t* d_query, int m, const Matrix& mat, int R,
+                               int n_strips, int32_t* prof, int8_t* prof2, int m_pad2,
+                               hipStream_t s);
+hipError_t launch_mode_empty_query(const int64_t* offs, int64_t n_seqs, int mode, int go, int ge,
+                                   int32_t* out, hipStream_t s);
+// R in {16, 32}; mode SW_MODE_GLOBAL or SW_MODE_SEMIGLOBAL
+hipError_t launch_mode_inter(int R, int mode, const ModeArgs& a, hipStream_t s);
+// Top-k of scores[0 .. n): items[0 .. k) = {sequence, 0}, best first
+// (1 <= k <= min(n, SW_MAX_TOPK)); gt and ties hold k int32 each.
+hipError_t launch_topk(const int32_t* scores, int64_t n, int32_t k, TopkState* st, int32_t* gt,
+                       int32_t* ties, int2* items, hipStream_t s);
+// hits[i] = {items[i].x, 0, -1, -1}: the hit list of an empty query.
+hipError_t launch_empty_hits(const int2* items, int32_t k, int4* hits, hipStream_t s);
 // Pair profiles for `n_pairs` pairs and intra-task profiles for `n_queries`
 // queries of a batch (see k_misc.hip for the layouts).
 hipError_t launch_batch_profiles(const uint8_t* d_queries, const int64_t* d_qoffs, int n_queries,

@@ -89,11 +89,45 @@ __device__ __forceinline__ void unpack_profile<8>(const uint2& v, int (&p)[8]) {
 
 __device__ __forceinline__ int imax(int a, int b) { return a > b ? a : b; }
 
-template <int R, int W2>
+// (score s, column c, row r) comes before (s2, c2, r2) as the end of a best
+// alignment: a higher score, else the smaller column, else the smaller row
+__device__ __forceinline__ bool end_before(int s, int c, int r, int s2, int c2, int r2) {
+  return s > s2 || (s == s2 && (c < c2 || (c == c2 && r < r2)));
+}
+
+// kEnds: also find where the best local alignment ends - the cell (i, j)
+// holding the maximum that comes first in database-then-query order
+// (smallest column j, then smallest row i) - and write {sid, score, i, j}
+// (0-based residue indices, -1 for a score of 0) to a.ends[item] instead of
+// the score to a.out.  Within one pass a lane meets its cells in that order
+// (columns advance with the step, rows with k inside a step), so a strict
+// "greater" keeps the first; passes, lanes and waves are merged comparing
+// (score, column, row).  Pad rows and columns never come first: with
+// open > 0 a gap value stays below the maximum it came from, and with
+// open = 0 a pad cell can only repeat a value some real cell earlier in
+// (column, row) order already holds.
+//
+// kVarGlobal, kVarSemi: the global and semi-global scores of the same
+// recurrence without the floor at 0 (the borders and score of each are
+// stated where the inter-task form k_mode_inter is defined): the first pass
+// is fed the top border row, every pass starts its rows at the left border,
+// a lane keeps its rows at the border while its column is still negative
+// (so the lane below reads the border as its diagonal), and the lane holding
+// the query's last row reads the score from the sequence's own columns in
+// the last pass.
+enum { kVarScore = 0, kVarEnds = 1, kVarGlobal = 2, kVarSemi = 3 };
+constexpr int kNegInf = -(1 << 29);
+
+__device__ __forceinline__ int gapw(int k, int go, int ge) { return k == 0 ? 0 : go + (k - 1) * ge; }
+
+template <int R, int W2, int V>
 __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
+  constexpr bool kEnds = V == kVarEnds;
+  constexpr bool kLocal = V == kVarScore || V == kVarEnds;
   constexpr int ROWS = 64 * R;   // query rows per pass
   __shared__ __align__(16) int8_t lprof_all[W2][kIntraCodes * ROWS];
   __shared__ int lbest[W2];
+  __shared__ int lpos[kEnds ? 2 * W2 : 1];
   typedef typename ProfVec<R>::T PV;
 
   const int lane = threadIdx.x & 63;
@@ -125,6 +159,10 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
       fcode_n = jf < n ? (int)bseq[jf] : SW_PAD_CODE;
       fh_n = 0;
       ff_n = 0;
+      if (!kLocal && p == 0) {      // the top border row H(0, j), F(0, j)
+        fh_n = V == kVarGlobal ? -gapw(jf + 1, go, ge) : 0;
+        ff_n = kNegInf;
+      }
       if (p > 0 && jf < n) {
         const int2 v = rb[jf];
         fh_n = v.x;
@@ -132,7 +170,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
       }
     };
 
-    int best = 0;
+    int best = kLocal ? 0 : kNegInf;
+    int bcol = INT32_MAX, brow = INT32_MAX;   // kEnds: first cell holding `best`
+    const int lstar = (a.m - 1) % ROWS / R, kstar = (a.m - 1) % R;   // the last row (modes)
     if (w == 0 && my_rounds > 0) fetch(0, 0);
     for (int T = 0; T < kSkew * w; ++T) {
       if (T == kSkew * w - 1 && my_rounds > 0) fetch(w, 0);
@@ -156,9 +196,15 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
       }
       int H[R], E[R];
+      const int top = p * ROWS + lane * R;      // rows top + 1 .. top + R (1-based)
 #pragma unroll
-      for (int k = 0; k < R; ++k) { H[k] = 0; E[k] = 0; }
-      int hdiag = 0, code = SW_PAD_CODE, hbot = 0, fbot = 0;
+      for (int k = 0; k < R; ++k) {
+        H[k] = kLocal ? 0 : -gapw(top + k + 1, go, ge);   // H(i, 0)
+        E[k] = kLocal ? 0 : H[k] - go;                    // E(i, 1)
+      }
+      int hdiag = kLocal ? 0 : -gapw(top, go, ge), code = SW_PAD_CODE;
+      int hbot = H[R - 1], fbot = 0;
+      int pbest = 0, pcol = 0, pk = 0;          // kEnds: this pass's first maximum
       for (int c = 0; c < C2; ++c) {
         int fcode = fcode_n, fh = fh_n, ff = ff_n;
         if (c + 1 < C2) fetch(p, c + 1);
@@ -178,15 +224,39 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
           int hd = hdiag;
           hdiag = hup;
           int F = fup;
+          const int col = c * 64 + tau - lane;    // this step's column
+          if (kLocal || col >= 0) {
 #pragma unroll
-          for (int k = 0; k < R; ++k) {
-            const int h = imax(imax(hd + prof[k], E[k]), F);
-            hd = H[k];
-            H[k] = h;
-            best = imax(best, h);
-            const int t = h - go;
-            E[k] = imax(imax(E[k] - ge, t), 0);
-            F = imax(imax(F - ge, t), 0);
+            for (int k = 0; k < R; ++k) {
+              const int h = imax(imax(hd + prof[k], E[k]), F);
+              hd = H[k];
+              H[k] = h;
+              if constexpr (kEnds) {
+                if (h > pbest) { pbest = h; pcol = col; pk = k; }
+              } else if constexpr (kLocal) {
+                best = imax(best, h);
+              }
+              const int t = h - go;
+              if constexpr (kLocal) {
+                E[k] = imax(imax(E[k] - ge, t), 0);
+                F = imax(imax(F - ge, t), 0);
+              } else {
+                E[k] = imax(E[k] - ge, t);
+                F = imax(F - ge, t);
+              }
+            }
+          }
+          if constexpr (!kLocal) {
+            if (last_pass && lane == lstar && col >= 0 && col < n) {
+              int v = H[0];
+#pragma unroll
+              for (int k = 1; k < R; ++k) v = k == kstar ? H[k] : v;
+              if (V == kVarGlobal) {
+                if (col == n - 1) best = v;
+              } else {
+                best = imax(best, v);
+              }
+            }
           }
           hbot = H[R - 1];
           fbot = F;
@@ -197,19 +267,49 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
         if (!last_pass && jo >= 0 && jo < n) rb[jo] = make_int2(collh, collf);
         __syncthreads();
       }
+      if constexpr (kEnds) {
+        const int prow = p * ROWS + lane * R + pk;
+        if (pbest > best || (pbest == best && pbest > 0 &&
+                             (pcol < bcol || (pcol == bcol && prow < brow)))) {
+          best = pbest;
+          bcol = pcol;
+          brow = prow;
+        }
+      }
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
     for (int T = kSkew * w + my_rounds * C2; T < T_total; ++T) __syncthreads();
 
+    if constexpr (kEnds) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) best = imax(best, __shfl_xor(best, off, 64));
-    if (lane == 0) lbest[w] = best;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int b = lbest[0];
+      for (int off = 32; off > 0; off >>= 1) {
+        const int ob = __shfl_xor(best, off, 64);
+        const int oc = __shfl_xor(bcol, off, 64);
+        const int orow = __shfl_xor(brow, off, 64);
+        if (end_before(ob, oc, orow, best, bcol, brow)) { best = ob; bcol = oc; brow = orow; }
+      }
+      if (lane == 0) { lbest[w] = best; lpos[2 * w] = bcol; lpos[2 * w + 1] = brow; }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int b = lbest[0], bc = lpos[0], br = lpos[1];
 #pragma unroll
-      for (int x = 1; x < W2; ++x) b = imax(b, lbest[x]);
-      a.out[qd.out_off + sid] = b;
+        for (int x = 1; x < W2; ++x)
+          if (end_before(lbest[x], lpos[2 * x], lpos[2 * x + 1], b, bc, br)) {
+            b = lbest[x]; bc = lpos[2 * x]; br = lpos[2 * x + 1];
+          }
+        a.ends[it] = b > 0 ? make_int4(sid, b, br, bc) : make_int4(sid, 0, -1, -1);
+      }
+    } else {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) best = imax(best, __shfl_xor(best, off, 64));
+      if (lane == 0) lbest[w] = best;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int b = lbest[0];
+#pragma unroll
+        for (int x = 1; x < W2; ++x) b = imax(b, lbest[x]);
+        a.out[qd.out_off + sid] = (kLocal || n > 0) ? b : -gapw(a.m, go, ge);
+      }
     }
     __syncthreads();
   }
@@ -410,7 +510,14 @@ hipError_t launch_pair_rw(int grid, const IntraPairArgs& a, hipStream_t s) {
 
 template <int R, int W2>
 hipError_t launch_rw(int grid, const IntraArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_intra_i32<R, W2>), dim3(grid), dim3(64 * W2), 0, s, a);
+  if (a.mode == SW_MODE_GLOBAL)
+    hipLaunchKernelGGL((k_intra_i32<R, W2, kVarGlobal>), dim3(grid), dim3(64 * W2), 0, s, a);
+  else if (a.mode == SW_MODE_SEMIGLOBAL)
+    hipLaunchKernelGGL((k_intra_i32<R, W2, kVarSemi>), dim3(grid), dim3(64 * W2), 0, s, a);
+  else if (a.ends)
+    hipLaunchKernelGGL((k_intra_i32<R, W2, kVarEnds>), dim3(grid), dim3(64 * W2), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_intra_i32<R, W2, kVarScore>), dim3(grid), dim3(64 * W2), 0, s, a);
   return hipGetLastError();
 }
 

@@ -6,11 +6,16 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <functional>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include <atomic>
+#include <thread>
+
+#include "cpu_scorer.h"
 #include "internal.h"
 #include "layout.h"
 
@@ -158,6 +163,11 @@ struct DbData {
   DevBuf<int2> d_long_items;        // {sid, 0} for the long list
   DevBuf<int2> d_long_pairs;        // {sid a, sid b or -1}: the long list in pairs
   int64_t n_long_pairs = 0;
+  // host copies for the hybrid search's CPU share: residues, offsets, bin
+  // descriptors {res_off, rb_off, len, slot0} and slots
+  std::vector<uint8_t> h_res;
+  std::vector<int64_t> h_offs, h_bins;
+  std::vector<int32_t> h_slots;
 };
 
 // Everything one search mutates: scratch buffers, streams, events, the
@@ -177,10 +187,15 @@ struct Searcher {
   BatchPlan batch;
   DevBuf<uint4> rb_batch;           // per-workgroup boundary rows of the batched kernel
   DevBuf<int32_t> counter;          // work-queue head of the batched kernel
+  DevBuf<int32_t> topk;             // top-k selection state, candidates, hit items
+  DevBuf<int4> hits_stage;          // hit list of host-buffer top-k calls
+  DevBuf<int32_t> mprof;            // int32 strip profile of global / semi-global searches
+  DevBuf<int2> rb_mode;             // their boundary rows, 8 bytes per short-bin cell column
   hipStream_t own_stream = nullptr; // host-buffer calls and batch graphs
   hipStream_t aux_stream = nullptr; // long-sequence kernel, overlapped
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_caller = nullptr;   // end of the last work enqueued on a caller's stream
+  hipEvent_t ev_chunk[2] = {nullptr, nullptr};   // hybrid search: GPU chunks in flight
   // timing: (kind, start, end) event pairs recorded since the last
   // sw_get_stats; events are recycled through `ev_pool`
   struct Timed { int kind; hipEvent_t a, b; };
@@ -221,9 +236,11 @@ void release_searcher(Searcher* db) {
   db->prof.release(); db->prof2.release(); db->prof3.release(); db->q_stage.release();
   db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
+  db->topk.release(); db->hits_stage.release(); db->mprof.release(); db->rb_mode.release();
   if (db->users.caller_pending) (void)hipEventSynchronize(db->ev_caller);
   db->users.caller_pending = false;
-  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out, &db->ev_caller}) {
+  for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out, &db->ev_caller,
+                        &db->ev_chunk[0], &db->ev_chunk[1]}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
@@ -254,6 +271,8 @@ void bind_buffers(Searcher* S) {
   S->prof.users = u; S->prof2.users = u; S->prof3.users = u; S->q_stage.users = u;
   S->out_stage.users = u;
   S->rb_batch.users = S->counter.users = S->flags.users = u;
+  S->topk.users = S->hits_stage.users = u;
+  S->mprof.users = S->rb_mode.users = u;
   BatchPlan& B = S->batch;
   B.pairs.users = u; B.qdesc.users = u; B.items.users = u; B.long_items.users = u;
   B.qoffs_d.users = u; B.prof.users = u; B.prof2.users = u;
@@ -289,7 +308,8 @@ int init_searcher(Searcher* S, DbData* d) {
   S->users.own[0] = S->own_stream;
   S->users.own[1] = S->aux_stream;
   S->users.any = true;
-  for (hipEvent_t* ev : {&S->ev_fork, &S->ev_join, &S->ev_in, &S->ev_out, &S->ev_caller})
+  for (hipEvent_t* ev : {&S->ev_fork, &S->ev_join, &S->ev_in, &S->ev_out, &S->ev_caller,
+                         &S->ev_chunk[0], &S->ev_chunk[1]})
     if ((e = hipEventCreateWithFlags(ev, hipEventDisableTiming)) != hipSuccess)
       return hip_fail(e, "event creation");
   S->users.caller_done = S->ev_caller;
@@ -470,6 +490,99 @@ int32_t effective_limit(int32_t requested) {
   return std::max<int32_t>(0, std::min<int32_t>(requested, kHalfExact));
 }
 
+// Row length of a query's intra-task profiles: a whole number of the
+// largest pass (64 lanes x 8 rows), so every (R, W2) can read them.
+int intra_rows_pad(int m) { return (m + 511) / 512 * 512; }
+
+// Schedule of one single-query search: inter-task strips (R rows, W waves),
+// the packed long-sequence kernel (RR, W2), the rescoring kernel (RRr, W2r)
+// and the intra-task profiles' row length.
+struct SearchShape {
+  int R, W, m_pad, n_strips, RR, W2, RRr, W2r, m_pad2;
+};
+
+SearchShape search_shape(const Searcher* db, int m) {
+  SearchShape sh{};
+  sh.R = kDefaultRows;
+  sh.W = kDefaultWaves;
+  pick_schedule(db, m, &sh.R, &sh.W);
+  sh.m_pad = (m + sh.R - 1) / sh.R * sh.R;
+  sh.n_strips = sh.m_pad / sh.R;
+  sh.RR = 8; sh.W2 = 1; sh.RRr = 8; sh.W2r = 1;
+  pick_intra(db, m, 8, &sh.RR, &sh.W2, true);   // long sequences, in pairs (binary16)
+  pick_intra(db, m, 2, &sh.RRr, &sh.W2r);       // exact rescoring (usually empty)
+  // the intra-task profiles serve every intra-task launch of the query (long
+  // list, rescoring, hit ends): pad to the largest pass, 64 x 8 rows
+  sh.m_pad2 = intra_rows_pad(m);
+  return sh;
+}
+
+// Device scratch of one single-query search.
+struct SearchScratch {
+  uint4* rb = nullptr;        // boundary rows of every short bin, zero on entry
+  int32_t* flags = nullptr;   // rescoring list: [0] count, {sid, query} pairs from +2
+  uint32_t* prof = nullptr;   // inter-task strip profile
+  int8_t* prof2 = nullptr;    // intra-task int8 profile
+  uint32_t* prof3 = nullptr;  // packed intra-task profile (long list present)
+  int2* rb_long = nullptr;    // per-workgroup rows of the long-sequence kernel
+  int grid_long = 0;
+  int2* rb_resc = nullptr;    // per-workgroup rows of the rescoring kernel
+  int grid_resc = 0;
+};
+
+// Element counts of the scratch pieces above for a query of this shape.
+struct ScratchSizes {
+  size_t rb, flags, prof, prof2, prof3, rb_long, rb_resc;   // elements of each type
+};
+
+ScratchSizes scratch_sizes(const Searcher* db, const SearchShape& sh, int grid_long,
+                           int grid_resc) {
+  const Plan& P = db->d->plan;
+  ScratchSizes z{};
+  z.rb = (size_t)std::max<int64_t>(P.boundary_uint4, 1);
+  z.flags = (size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1));
+  z.prof = (size_t)sh.n_strips * prof_strip_dwords(sh.R);
+  z.prof2 = (size_t)kIntraCodes * sh.m_pad2;
+  z.prof3 = P.n_long > 0 ? (size_t)kIntraCodes * (sh.m_pad2 / 2) : 0;
+  z.rb_long = (size_t)grid_long * (size_t)std::max<int32_t>(P.max_long_len, 1);
+  z.rb_resc = (size_t)grid_resc * (size_t)rescore_stride(P);
+  return z;
+}
+
+// Launches the inter-task kernel over the short bins (a.bin_begin and the
+// count are the runner's); returns SW_OK or an error code.
+typedef std::function<int(InterArgs& a, int R, int W, hipStream_t s)> BinRunner;
+
+int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScratch& X,
+                           const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
+                           int32_t ge, int32_t* d_out, hipStream_t s,
+                           const BinRunner* bins = nullptr);
+
+// The searcher's own scratch for a query of this shape, grown as needed.
+int reserve_search_scratch(Searcher* db, const SearchShape& sh, SearchScratch* X) {
+  hipError_t e;
+  const int64_t n_long = db->d->plan.n_long;
+  if ((e = db->prof.reserve((size_t)sh.n_strips * prof_strip_dwords(sh.R))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
+  if ((e = db->prof2.reserve((size_t)kIntraCodes * sh.m_pad2)) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
+  if (n_long > 0 && (e = db->prof3.reserve((size_t)kIntraCodes * (sh.m_pad2 / 2))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
+  const int grid_long = (int)std::min<int64_t>(db->d->n_long_pairs, kIntraGridLong);
+  if (n_long > 0 && (e = reserve_long_scratch(db, grid_long)) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
+  X->rb = db->rb.p;
+  X->flags = db->flags.p;
+  X->prof = db->prof.p;
+  X->prof2 = db->prof2.p;
+  X->prof3 = n_long > 0 ? db->prof3.p : nullptr;
+  X->rb_long = db->rb_long.p;
+  X->grid_long = grid_long;
+  X->rb_resc = db->rb_resc.p;
+  X->grid_resc = kIntraGridRescore;
+  return SW_OK;
+}
+
 int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
                    int32_t ge, int32_t* d_out, hipStream_t s) {
   hipError_t e;
@@ -478,29 +591,27 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     e = launch_fill(d_out, db->d->n_seqs, 0, s);
     return e == hipSuccess ? SW_OK : hip_fail(e, "fill");
   }
-  int R = kDefaultRows, W = kDefaultWaves;
-  pick_schedule(db, m, &R, &W);
-  const int m_pad = (m + R - 1) / R * R;
-  const int n_strips = m_pad / R;
-  const int64_t n_long = db->d->plan.n_long;
-  int RR = 8, W2 = 1, RRr = 8, W2r = 1;
-  pick_intra(db, m, 8, &RR, &W2, true);   // long sequences, in pairs (binary16)
-  pick_intra(db, m, 2, &RRr, &W2r);       // exact rescoring (usually empty)
-  // the intra-task profiles of both launches: pad to the larger pass
-  const int rows2 = 64 * std::max(RR, RRr);
-  const int m_pad2 = (m + rows2 - 1) / rows2 * rows2;
+  const SearchShape sh = search_shape(db, m);
+  SearchScratch X;
+  const int rc = reserve_search_scratch(db, sh, &X);
+  if (rc != SW_OK) return rc;
+  return enqueue_search_kernels(db, sh, X, d_query, m, mat, go, ge, d_out, s);
+}
 
-  if ((e = db->prof.reserve((size_t)n_strips * prof_strip_dwords(R))) != hipSuccess)
-    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
-  if ((e = db->prof2.reserve((size_t)kIntraCodes * m_pad2)) != hipSuccess)
-    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
-  if (n_long > 0 && (e = db->prof3.reserve((size_t)kIntraCodes * (m_pad2 / 2))) != hipSuccess)
-    return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
+// The kernels of one search (profile, long list, inter-task bins,
+// rescoring) on stream s with the given scratch.  m > 0, n_seqs > 0.
+int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScratch& X,
+                           const uint8_t* d_query, int32_t m, const Matrix& mat, int32_t go,
+                           int32_t ge, int32_t* d_out, hipStream_t s, const BinRunner* bins) {
+  hipError_t e;
+  const int R = sh.R, W = sh.W, RR = sh.RR, W2 = sh.W2, RRr = sh.RRr, W2r = sh.W2r;
+  const int m_pad2 = sh.m_pad2;
+  const int64_t n_long = db->d->plan.n_long;
+  int2* const flist = reinterpret_cast<int2*>(X.flags + 2);
 
   const int t_total = time_begin(db, kTimeTotal, s);
-  if ((e = launch_profile(d_query, m, mat, db->prof.p, m_pad, R, db->prof2.p,
-                          n_long > 0 ? db->prof3.p : nullptr, m_pad2, db->flags.p, s)) !=
-      hipSuccess)
+  if ((e = launch_profile(d_query, m, mat, X.prof, sh.m_pad, R, X.prof2,
+                          n_long > 0 ? X.prof3 : nullptr, m_pad2, X.flags, s)) != hipSuccess)
     return hip_fail(e, "profile kernel");
 
   // long sequences: packed intra-task kernel on the auxiliary stream,
@@ -508,7 +619,7 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   IntraArgs ia{};
   ia.res = db->d->res.p;
   ia.offs = db->d->offs.p;
-  ia.prof2 = db->prof2.p;
+  ia.prof2 = X.prof2;
   ia.q0.prof2_off = 0;
   ia.q0.out_off = 0;
   ia.q0.m_pad2 = m_pad2;
@@ -525,22 +636,19 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     la.offs = db->d->offs.p;
     la.items = db->d->d_long_pairs.p;
     la.count = (int32_t)db->d->n_long_pairs;
-    la.prof3 = db->prof3.p;
+    la.prof3 = X.prof3;
     la.m_pad2 = m_pad2;
     la.n_pass = (m + 64 * RR - 1) / (64 * RR);
     la.go2 = half_pair(go);
     la.ge2 = half_pair(ge);
     la.sat_limit = effective_limit(db->sat_limit);
-    const int grid = (int)std::min<int64_t>(db->d->n_long_pairs, kIntraGridLong);
-    if ((e = reserve_long_scratch(db, grid)) != hipSuccess)
-      return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
-    la.scratch = db->rb_long.p;
+    la.scratch = X.rb_long;
     la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
     la.out = d_out;
-    la.flag_count = db->flags.p;
-    la.flag_list = flag_list(db);
+    la.flag_count = X.flags;
+    la.flag_list = flist;
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
-    if ((e = launch_intra_pairs(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
+    if ((e = launch_intra_pairs(RR, W2, X.grid_long, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
     time_end(db, tl, db->aux_stream);
     if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
@@ -552,18 +660,21 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   a.res2 = reinterpret_cast<const uint2*>(db->d->packed.p);
   a.bins = db->d->bins.p;
   a.bin_begin = 0;
-  a.n_strips = n_strips;
-  a.prof = db->prof.p;
+  a.n_strips = sh.n_strips;
+  a.prof = X.prof;
   a.go2 = half_pair(go);
   a.ge2 = half_pair(ge);
-  a.rb = db->rb.p;
+  a.rb = X.rb;
   a.slot_seq = db->d->slot_seq.p;
   a.out = d_out;
-  a.flag_count = db->flags.p;
-  a.flag_list = flag_list(db);
+  a.flag_count = X.flags;
+  a.flag_list = flist;
   a.sat_limit = effective_limit(db->sat_limit);
   const int n_bins = (int)db->d->plan.n_bins;
-  if (n_bins > 0) {
+  if (bins) {
+    const int rc = (*bins)(a, R, W, s);
+    if (rc != SW_OK) return rc;
+  } else if (n_bins > 0) {
     const int ti = time_begin(db, kTimeInter, s);
     if ((e = launch_inter(R, W, n_bins, a, s)) != hipSuccess) return hip_fail(e, "inter-task kernel");
     time_end(db, ti, s);
@@ -576,14 +687,14 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
     // exact rescoring of sequences whose half-precision score reached the
     // limit; the workgroups read the list's length on the device
     IntraArgs ra = ia;
-    ra.items = flag_list(db);
-    ra.count_ptr = db->flags.p;
+    ra.items = flist;
+    ra.count_ptr = X.flags;
     ra.count = 0;
-    ra.scratch = db->rb_resc.p;
+    ra.scratch = X.rb_resc;
     ra.scratch_stride = rescore_stride(db->d->plan);
     ra.q0.n_pass = (m + 64 * RRr - 1) / (64 * RRr);
     const int tr = time_begin(db, kTimeRescore, s);
-    if ((e = launch_intra(RRr, W2r, kIntraGridRescore, ra, s)) != hipSuccess)
+    if ((e = launch_intra(RRr, W2r, X.grid_resc, ra, s)) != hipSuccess)
       return hip_fail(e, "rescoring kernel");
     time_end(db, tr, s);
   }
@@ -594,6 +705,153 @@ int enqueue_search(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix
   const int64_t long_res = db->d->long_residues;
   db->stats.inter_cells += (int64_t)m * (db->d->n_res - long_res);
   db->stats.intra_cells += (int64_t)m * long_res;
+  return SW_OK;
+}
+
+// The k best hits of the score row d_scores of a query just searched on
+// stream s (its intra-task profile is still in db->prof2): device top-k
+// selection, then the exact 32-bit intra-task kernel with end tracking over
+// the k hit sequences, writing {seq, score, query end, db end} to d_hits.
+int enqueue_hits(Searcher* db, int32_t m, int32_t go, int32_t ge, const int32_t* d_scores,
+                 int32_t k, sw_hit* d_hits, hipStream_t s) {
+  hipError_t e;
+  const int64_t n = db->d->n_seqs;
+  k = (int32_t)std::min<int64_t>(k, n);
+  if (k <= 0) return SW_OK;
+  const size_t st_words = sizeof(TopkState) / 4;
+  if ((e = db->topk.reserve(st_words + 4 * (size_t)k)) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("top-k scratch: ") + hipGetErrorString(e));
+  TopkState* st = reinterpret_cast<TopkState*>(db->topk.p);
+  int32_t* gt = db->topk.p + st_words;
+  int32_t* ties = gt + k;
+  int2* items = reinterpret_cast<int2*>(ties + k);
+  if ((e = launch_topk(d_scores, n, k, st, gt, ties, items, s)) != hipSuccess)
+    return hip_fail(e, "top-k kernels");
+  if (m == 0) {   // empty query: every score 0, no ends
+    if ((e = launch_empty_hits(items, k, reinterpret_cast<int4*>(d_hits), s)) != hipSuccess)
+      return hip_fail(e, "hit list");
+    return SW_OK;
+  }
+  int RR = 8, W2 = 1;
+  pick_intra(db, m, 8, &RR, &W2);
+  IntraArgs ea{};
+  ea.res = db->d->res.p;
+  ea.offs = db->d->offs.p;
+  ea.items = items;
+  ea.count_ptr = nullptr;
+  ea.count = k;
+  ea.prof2 = db->prof2.p;
+  ea.q0.prof2_off = 0;
+  ea.q0.out_off = 0;
+  ea.q0.m_pad2 = intra_rows_pad(m);
+  ea.q0.n_pass = (m + 64 * RR - 1) / (64 * RR);
+  ea.queries = nullptr;
+  ea.go = go;
+  ea.ge = ge;
+  ea.scratch = db->rb_resc.p;
+  ea.scratch_stride = rescore_stride(db->d->plan);
+  ea.out = nullptr;
+  ea.ends = reinterpret_cast<int4*>(d_hits);
+  const int grid = std::min<int>(k, kIntraGridRescore);
+  if ((e = launch_intra(RR, W2, grid, ea, s)) != hipSuccess) return hip_fail(e, "hit-end kernel");
+  return SW_OK;
+}
+
+// Largest magnitude a global or semi-global score may reach (the kernels'
+// -infinity is -2^29).
+constexpr int64_t kModeRange = int64_t(1) << 28;
+
+// Bound on the magnitude of every value a global / semi-global search of a
+// query of length m computes: gaps over every row and column of the padded
+// matrix plus 128 per cell step.
+int64_t mode_bound(const Searcher* db, int64_t m, int64_t go, int64_t ge) {
+  return go + (ge + 128) * (m + 512 + (int64_t)db->d->plan.max_len + 1024);
+}
+
+// Global / semi-global search of one query: the int32 inter-task kernel over
+// the short bins and the int32 wavefront kernel over the long list, on the
+// auxiliary stream beside it.
+int enqueue_search_mode(Searcher* db, const uint8_t* d_query, int32_t m, const Matrix& mat,
+                        int32_t go, int32_t ge, int mode, int32_t* d_out, hipStream_t s) {
+  hipError_t e;
+  const Plan& P = db->d->plan;
+  const int64_t n = db->d->n_seqs;
+  if (n == 0) return SW_OK;
+  if (m == 0) {
+    if ((e = launch_mode_empty_query(db->d->offs.p, n, mode, go, ge, d_out, s)) != hipSuccess)
+      return hip_fail(e, "empty-query kernel");
+    return SW_OK;
+  }
+  // 16 or 32 rows per strip: the fewer padded rows (32 on a tie)
+  const int R = ((m + 15) / 16 * 16 < (m + 31) / 32 * 32) ? 16 : 32;
+  const int n_strips = (m + R - 1) / R;
+  const int m_pad2 = intra_rows_pad(m);
+  const int64_t short_dwords = P.n_bins < P.n_bins + P.n_long_bins ? P.bins[4 * P.n_bins]
+                                                                  : P.packed_dwords;
+  if ((e = db->mprof.reserve((size_t)n_strips * kProfRowDwords * R)) != hipSuccess ||
+      (e = db->prof2.reserve((size_t)kIntraCodes * m_pad2)) != hipSuccess ||
+      (e = db->rb_mode.reserve((size_t)std::max<int64_t>(4 * short_dwords, 1))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("mode search scratch: ") + hipGetErrorString(e));
+  const int t_total = time_begin(db, kTimeTotal, s);
+  if ((e = launch_mode_profile(d_query, m, mat, R, n_strips, db->mprof.p, db->prof2.p, m_pad2,
+                               s)) != hipSuccess)
+    return hip_fail(e, "profile kernel");
+  const int64_t n_long = P.n_long;
+  if (n_long > 0) {
+    if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
+      return hip_fail(e, "stream wait");
+    int RR = 8, W2 = 1;
+    pick_intra(db, m, 8, &RR, &W2);
+    const int grid = (int)std::min<int64_t>(n_long, kIntraGridLong);
+    if ((e = reserve_long_scratch(db, grid)) != hipSuccess)
+      return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
+    IntraArgs la{};
+    la.res = db->d->res.p;
+    la.offs = db->d->offs.p;
+    la.items = db->d->d_long_items.p;
+    la.count = (int32_t)n_long;
+    la.prof2 = db->prof2.p;
+    la.q0.m_pad2 = m_pad2;
+    la.q0.n_pass = (m + 64 * RR - 1) / (64 * RR);
+    la.go = go;
+    la.ge = ge;
+    la.scratch = db->rb_long.p;
+    la.scratch_stride = std::max<int64_t>(P.max_long_len, 1);
+    la.out = d_out;
+    la.mode = mode;
+    la.m = m;
+    const int tl = time_begin(db, kTimeIntra, db->aux_stream);
+    if ((e = launch_intra(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
+      return hip_fail(e, "intra-task kernel");
+    time_end(db, tl, db->aux_stream);
+    if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
+      return hip_fail(e, "event");
+  }
+  if (P.n_bins > 0) {
+    ModeArgs a{};
+    a.res = db->d->packed.p;
+    a.bins = db->d->bins.p;
+    a.slot_seq = db->d->slot_seq.p;
+    a.offs = db->d->offs.p;
+    a.n_halfbins = (int32_t)(2 * P.n_bins);
+    a.n_strips = n_strips;
+    a.m = m;
+    a.go = go;
+    a.ge = ge;
+    a.prof = db->mprof.p;
+    a.rb = db->rb_mode.p;
+    a.out = d_out;
+    const int ti = time_begin(db, kTimeInter, s);
+    if ((e = launch_mode_inter(R, mode, a, s)) != hipSuccess)
+      return hip_fail(e, "inter-task mode kernel");
+    time_end(db, ti, s);
+  }
+  if (n_long > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
+    return hip_fail(e, "stream wait");
+  time_end(db, t_total, s);
+  db->stats.inter_cells += (int64_t)m * (db->d->n_res - db->d->long_residues);
+  db->stats.intra_cells += (int64_t)m * db->d->long_residues;
   return SW_OK;
 }
 
@@ -982,6 +1240,15 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
     destroy_db(h);
     return hip_fail(e, "database upload");
   }
+  try {
+    d->h_res.assign(residues, residues + d->n_res);
+    d->h_offs.assign(offsets, offsets + n_seqs + 1);
+    d->h_bins.swap(h_bins);
+    d->h_slots.swap(h_slots);
+  } catch (...) {
+    destroy_db(h);
+    return fail(SW_ENOMEM, "host copy allocation failed");
+  }
   if ((rc = init_searcher(&h->main, d)) != SW_OK) {
     std::string msg = get_error();
     destroy_db(h);
@@ -1057,6 +1324,304 @@ static int impl_search(swdb::Searcher* db, const uint8_t* query, int32_t query_l
   if (db->d->n_seqs > 0 &&
       (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)db->d->n_seqs * 4, hipMemcpyDeviceToHost,
                           s)) != hipSuccess)
+    return hip_fail(e, "score download");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
+  set_error("");
+  return SW_OK;
+}
+
+static int impl_search_topk_async(swdb::Searcher* db, const uint8_t* d_query, int32_t query_len,
+                                  const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                                  int32_t k, int32_t* d_out_scores, sw_hit* d_hits,
+                                  void* hip_stream) {
+  using namespace swdb;
+  int rc = validate_search(db, d_query, query_len, matrix, gap_open, gap_extend, d_out_scores);
+  if (rc != SW_OK) return rc;
+  if (k < 0) return fail(SW_EINVAL, "k < 0");
+  if (k > SW_MAX_TOPK) return fail(SW_ERANGE, "k > SW_MAX_TOPK");
+  if (k > 0 && db->d->n_seqs > 0 && !d_hits) return fail(SW_EINVAL, "hits is NULL");
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  rc = enqueue_search(db, d_query, query_len, mat, gap_open, gap_extend, d_out_scores, s);
+  if (rc == SW_OK) rc = enqueue_hits(db, query_len, gap_open, gap_extend, d_out_scores, k, d_hits, s);
+  mark_caller_work(db, s);
+  if (rc == SW_OK) set_error("");
+  return rc;
+}
+
+static int impl_search_topk(swdb::Searcher* db, const uint8_t* query, int32_t query_len,
+                            const int8_t* matrix, int32_t gap_open, int32_t gap_extend, int32_t k,
+                            int32_t* out_scores, sw_hit* out_hits) {
+  using namespace swdb;
+  // out_scores may be NULL here: pass any non-null pointer to the check
+  int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, matrix);
+  if (rc != SW_OK) return rc;
+  if (k < 0) return fail(SW_EINVAL, "k < 0");
+  if (k > SW_MAX_TOPK) return fail(SW_ERANGE, "k > SW_MAX_TOPK");
+  const int64_t n = db->d->n_seqs;
+  const int32_t kk = (int32_t)std::min<int64_t>(k, n);
+  if (kk > 0 && !out_hits) return fail(SW_EINVAL, "out_hits is NULL");
+  for (int32_t i = 0; i < query_len; ++i)
+    if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  hipError_t e;
+  if ((e = db->q_stage.reserve((size_t)std::max(query_len, 1))) != hipSuccess ||
+      (e = db->out_stage.reserve((size_t)std::max<int64_t>(n, 1))) != hipSuccess ||
+      (e = db->hits_stage.reserve((size_t)std::max(kk, 1))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
+  hipStream_t s = db->own_stream;
+  if (query_len > 0 &&
+      (e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
+          hipSuccess)
+    return hip_fail(e, "query upload");
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  rc = enqueue_search(db, db->q_stage.p, query_len, mat, gap_open, gap_extend, db->out_stage.p, s);
+  if (rc == SW_OK)
+    rc = enqueue_hits(db, query_len, gap_open, gap_extend, db->out_stage.p, kk,
+                      reinterpret_cast<sw_hit*>(db->hits_stage.p), s);
+  if (rc != SW_OK) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
+  if (out_scores && n > 0 &&
+      (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)n * 4, hipMemcpyDeviceToHost, s)) !=
+          hipSuccess)
+    return hip_fail(e, "score download");
+  if (kk > 0 && (e = hipMemcpyAsync(out_hits, db->hits_stage.p, (size_t)kk * sizeof(sw_hit),
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(e, "hit download");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
+  set_error("");
+  return SW_OK;
+}
+
+// ------------------------------------------------------------ hybrid search
+constexpr int64_t kHybridMinChunk = 32;   // bins per GPU launch, at least
+
+static void hybrid_score_bin(const swdb::DbData& D, const swdb::cpu::Profile& prof, int64_t b,
+                             int32_t go, int32_t ge, int32_t* out, swdb::cpu::Workspace* w,
+                             int64_t* cells) {
+  const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
+  for (int k = 0; k < SW_BIN_SEQS; ++k) {
+    const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
+    if (sid < 0) continue;
+    const int64_t at = D.h_offs[(size_t)sid];
+    const int n = (int)(D.h_offs[(size_t)sid + 1] - at);
+    out[sid] = swdb::cpu::score(prof, D.h_res.data() + at, n, go, ge, w);
+    *cells += (int64_t)n * prof.m;
+  }
+}
+
+static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t query_len,
+                              const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                              int32_t cpu_threads, int32_t* out_scores, sw_hybrid_stats* hst) {
+  using namespace swdb;
+  int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, out_scores);
+  if (rc != SW_OK) return rc;
+  if (cpu_threads < 0 || cpu_threads > 1024) return fail(SW_EINVAL, "cpu_threads must be 0..1024");
+  for (int32_t i = 0; i < query_len; ++i)
+    if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  const DbData& D = *db->d;
+  const int64_t n = D.n_seqs, n_bins = D.plan.n_bins;
+  sw_hybrid_stats st{};
+  const auto t0 = std::chrono::steady_clock::now();
+  const int threads = cpu_threads > 0 ? cpu_threads
+                                      : std::max(1, (int)std::thread::hardware_concurrency() - 1);
+  st.cpu_threads = threads;
+  if (n == 0 || query_len == 0) {
+    if (n > 0) memset(out_scores, 0, (size_t)n * 4);
+    if (hst) *hst = st;
+    set_error("");
+    return SW_OK;
+  }
+  hipError_t e;
+  if ((e = db->q_stage.reserve((size_t)query_len)) != hipSuccess ||
+      (e = db->out_stage.reserve((size_t)n)) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
+  std::vector<int32_t> gpu_scores;
+  cpu::Profile prof;
+  try {
+    gpu_scores.resize((size_t)n);
+    cpu::build_profile(query, query_len, matrix, &prof);
+  } catch (...) {
+    return fail(SW_ENOMEM, "host allocation failed");
+  }
+  hipStream_t s = db->own_stream;
+  if ((e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
+      hipSuccess)
+    return hip_fail(e, "query upload");
+  const SearchShape sh = search_shape(db, query_len);
+  SearchScratch X;
+  if ((rc = reserve_search_scratch(db, sh, &X)) != SW_OK) return rc;
+
+  // the shared work order: the GPU takes chunks of bins from the front
+  // (longest first), the host threads single bins from the back
+  std::mutex mu;
+  int64_t front = 0, back = n_bins;
+  std::atomic<int64_t> cpu_cells{0}, cpu_bins{0};
+  std::vector<std::thread> pool;
+  auto worker = [&]() {
+    cpu::Workspace w;
+    int64_t cells = 0, bins = 0;
+    for (;;) {
+      int64_t b;
+      {
+        std::lock_guard<std::mutex> l(mu);
+        if (back <= front) break;
+        b = --back;
+      }
+      hybrid_score_bin(D, prof, b, gap_open, gap_extend, out_scores, &w, &cells);
+      ++bins;
+    }
+    cpu_cells += cells;
+    cpu_bins += bins;
+  };
+  try {
+    for (int t = 0; t < threads; ++t) pool.emplace_back(worker);
+  } catch (...) {
+    std::lock_guard<std::mutex> l(mu);
+    back = front;   // no more host work
+  }
+  int64_t gpu_bins = 0;
+  BinRunner runner = [&](InterArgs& a, int R, int W, hipStream_t st_) -> int {
+    int k = 0;
+    for (;;) {
+      int64_t b0, take;
+      {
+        std::lock_guard<std::mutex> l(mu);
+        const int64_t rem = back - front;
+        if (rem <= 0) break;
+        take = std::min(rem, std::max(kHybridMinChunk, rem / 4));
+        b0 = front;
+        front += take;
+      }
+      a.bin_begin = (int32_t)b0;
+      hipError_t err;
+      if ((err = launch_inter(R, W, (int)take, a, st_)) != hipSuccess)
+        return hip_fail(err, "inter-task kernel");
+      if ((err = hipEventRecord(db->ev_chunk[k & 1], st_)) != hipSuccess)
+        return hip_fail(err, "event");
+      // keep at most two chunks queued: claim the next once the earlier ends
+      if (k > 0 && (err = hipEventSynchronize(db->ev_chunk[(k - 1) & 1])) != hipSuccess)
+        return hip_fail(err, "chunk wait");
+      ++db->stats.n_inter_launches;
+      gpu_bins += take;
+      ++k;
+    }
+    return SW_OK;
+  };
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  rc = enqueue_search_kernels(db, sh, X, db->q_stage.p, query_len, mat, gap_open, gap_extend,
+                              db->out_stage.p, s, &runner);
+  if (rc != SW_OK) {
+    std::lock_guard<std::mutex> l(mu);
+    back = front;
+  }
+  for (auto& t : pool) t.join();
+  if (rc == SW_OK &&
+      (e = hipMemcpyAsync(gpu_scores.data(), db->out_stage.p, (size_t)n * 4, hipMemcpyDeviceToHost,
+                          s)) != hipSuccess)
+    rc = hip_fail(e, "score download");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == SW_OK) rc = hip_fail(e, "search");
+  if (rc != SW_OK) return rc;
+  // GPU share: bins before the split point and the long list
+  const int64_t split = front;
+  for (int64_t b = 0; b < split; ++b) {
+    const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
+    for (int k = 0; k < SW_BIN_SEQS; ++k) {
+      const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
+      if (sid >= 0) out_scores[sid] = gpu_scores[(size_t)sid];
+    }
+  }
+  for (int32_t sid : D.long_ids) out_scores[sid] = gpu_scores[(size_t)sid];
+  st.gpu_bins = gpu_bins;
+  st.cpu_bins = cpu_bins.load();
+  st.cpu_cells = cpu_cells.load();
+  st.gpu_cells = (int64_t)query_len * D.n_res - st.cpu_cells;
+  st.ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (hst) *hst = st;
+  set_error("");
+  return SW_OK;
+}
+
+static int validate_mode(const swdb::Searcher* db, int32_t m, int32_t go, int32_t ge,
+                         int32_t mode) {
+  using namespace swdb;
+  if (mode != SW_MODE_LOCAL && mode != SW_MODE_GLOBAL && mode != SW_MODE_SEMIGLOBAL)
+    return fail(SW_EINVAL, "mode must be SW_MODE_LOCAL, SW_MODE_GLOBAL or SW_MODE_SEMIGLOBAL");
+  if (mode != SW_MODE_LOCAL && mode_bound(db, m, go, ge) > kModeRange)
+    return fail(SW_ERANGE, "gap penalties and lengths too large for 32-bit global scores");
+  return SW_OK;
+}
+
+static int impl_search_mode_async(swdb::Searcher* db, const uint8_t* d_query, int32_t query_len,
+                                  const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                                  int32_t mode, int32_t* d_out_scores, void* hip_stream) {
+  using namespace swdb;
+  int rc = validate_search(db, d_query, query_len, matrix, gap_open, gap_extend, d_out_scores);
+  if (rc == SW_OK) rc = validate_mode(db, query_len, gap_open, gap_extend, mode);
+  if (rc != SW_OK) return rc;
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  rc = mode == SW_MODE_LOCAL
+           ? enqueue_search(db, d_query, query_len, mat, gap_open, gap_extend, d_out_scores, s)
+           : enqueue_search_mode(db, d_query, query_len, mat, gap_open, gap_extend, mode,
+                                 d_out_scores, s);
+  mark_caller_work(db, s);
+  if (rc == SW_OK) set_error("");
+  return rc;
+}
+
+static int impl_search_mode(swdb::Searcher* db, const uint8_t* query, int32_t query_len,
+                            const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                            int32_t mode, int32_t* out_scores) {
+  using namespace swdb;
+  int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, out_scores);
+  if (rc == SW_OK) rc = validate_mode(db, query_len, gap_open, gap_extend, mode);
+  if (rc != SW_OK) return rc;
+  for (int32_t i = 0; i < query_len; ++i)
+    if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  hipError_t e;
+  if ((e = db->q_stage.reserve((size_t)std::max(query_len, 1))) != hipSuccess ||
+      (e = db->out_stage.reserve((size_t)std::max<int64_t>(db->d->n_seqs, 1))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
+  hipStream_t s = db->own_stream;
+  if (query_len > 0 &&
+      (e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
+          hipSuccess)
+    return hip_fail(e, "query upload");
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  rc = mode == SW_MODE_LOCAL
+           ? enqueue_search(db, db->q_stage.p, query_len, mat, gap_open, gap_extend,
+                            db->out_stage.p, s)
+           : enqueue_search_mode(db, db->q_stage.p, query_len, mat, gap_open, gap_extend, mode,
+                                 db->out_stage.p, s);
+  if (rc != SW_OK) {
+    (void)hipStreamSynchronize(s);
+    return rc;
+  }
+  if (db->d->n_seqs > 0 &&
+      (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)db->d->n_seqs * 4,
+                          hipMemcpyDeviceToHost, s)) != hipSuccess)
     return hip_fail(e, "score download");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "search");
   set_error("");
@@ -1365,6 +1930,89 @@ int sw_search_async(sw_db* h, const uint8_t* d_query, int32_t query_len, const i
                     int32_t gap_open, int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
   return impl_search_async(S_of(h), d_query, query_len, matrix, gap_open, gap_extend, d_out_scores,
                            hip_stream);
+}
+int sw_search_topk(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* out_scores,
+                   sw_hit* out_hits) {
+  return impl_search_topk(S_of(h), query, query_len, matrix, gap_open, gap_extend, k, out_scores,
+                          out_hits);
+}
+int sw_search_topk_async(sw_db* h, const uint8_t* d_query, int32_t query_len,
+                         const int8_t* matrix, int32_t gap_open, int32_t gap_extend, int32_t k,
+                         int32_t* d_out_scores, sw_hit* d_hits, void* hip_stream) {
+  return impl_search_topk_async(S_of(h), d_query, query_len, matrix, gap_open, gap_extend, k,
+                                d_out_scores, d_hits, hip_stream);
+}
+int sw_search_hybrid(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                     int32_t gap_open, int32_t gap_extend, int32_t cpu_threads,
+                     int32_t* out_scores, sw_hybrid_stats* stats) {
+  return impl_search_hybrid(S_of(h), query, query_len, matrix, gap_open, gap_extend, cpu_threads,
+                            out_scores, stats);
+}
+
+int sw_host_search(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
+                   const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t threads, int32_t* out_scores) {
+  using namespace swdb;
+  if (n_seqs < 0) return fail(SW_EINVAL, "n_seqs < 0");
+  if (n_seqs > 0 && (!offsets || !out_scores)) return fail(SW_EINVAL, "offsets or out_scores is NULL");
+  if (query_len < 0) return fail(SW_EINVAL, "query_len < 0");
+  if (query_len > SW_MAX_LEN) return fail(SW_ERANGE, "query longer than 2^24-1 residues");
+  if (query_len > 0 && !query) return fail(SW_EINVAL, "query is NULL");
+  if (!matrix) return fail(SW_EINVAL, "matrix is NULL");
+  if (gap_extend < 0 || gap_open < gap_extend)
+    return fail(SW_EINVAL, "gaps must satisfy 0 <= gap_extend <= gap_open");
+  if (gap_open > SW_MAX_GAP) return fail(SW_ERANGE, "gap_open > 2^30");
+  if (threads < 0 || threads > 1024) return fail(SW_EINVAL, "threads must be 0..1024");
+  if (n_seqs == 0) { set_error(""); return SW_OK; }
+  if (offsets[0] != 0) return fail(SW_EINVAL, "offsets[0] must be 0");
+  for (int64_t i = 0; i < n_seqs; ++i) {
+    if (offsets[i + 1] < offsets[i]) return fail(SW_EINVAL, "offsets must be non-decreasing");
+    if (offsets[i + 1] - offsets[i] > SW_MAX_LEN)
+      return fail(SW_ERANGE, "sequence longer than 2^24-1 residues");
+  }
+  if (offsets[n_seqs] > 0 && !residues) return fail(SW_EINVAL, "residues is NULL");
+  for (int64_t i = 0; i < offsets[n_seqs]; ++i)
+    if (residues[i] >= SW_ALPHA) return fail(SW_EINVAL, "residue code >= 24");
+  for (int32_t i = 0; i < query_len; ++i)
+    if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24");
+  cpu::Profile prof;
+  try {
+    cpu::build_profile(query, query_len, matrix, &prof);
+  } catch (...) {
+    return fail(SW_ENOMEM, "host allocation failed");
+  }
+  const int nt = threads > 0 ? threads : std::max(1, (int)std::thread::hardware_concurrency());
+  std::atomic<int64_t> next{0};
+  auto worker = [&]() {
+    cpu::Workspace w;
+    for (int64_t i; (i = next.fetch_add(1)) < n_seqs;) {
+      const int64_t at = offsets[i];
+      out_scores[i] = cpu::score(prof, residues + at, (int)(offsets[i + 1] - at), gap_open,
+                                 gap_extend, &w);
+    }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int t = 1; t < nt; ++t) pool.emplace_back(worker);
+  } catch (...) {
+  }
+  worker();
+  for (auto& t : pool) t.join();
+  set_error("");
+  return SW_OK;
+}
+
+int sw_search_mode(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                   int32_t gap_open, int32_t gap_extend, int32_t mode, int32_t* out_scores) {
+  return impl_search_mode(S_of(h), query, query_len, matrix, gap_open, gap_extend, mode,
+                          out_scores);
+}
+int sw_search_mode_async(sw_db* h, const uint8_t* d_query, int32_t query_len,
+                         const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                         int32_t mode, int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_mode_async(S_of(h), d_query, query_len, matrix, gap_open, gap_extend, mode,
+                                d_out_scores, hip_stream);
 }
 int sw_search_batch(sw_db* h, const uint8_t* queries, const int64_t* query_offsets,
                     int32_t n_queries, const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
