@@ -159,9 +159,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
       fcode_n = jf < n ? (int)bseq[jf] : SW_PAD_CODE;
       fh_n = 0;
       ff_n = 0;
-      if (!kLocal && p == 0) {      // the top border row H(0, j), F(0, j)
-        fh_n = V == kVarGlobal ? -gapw(jf + 1, go, ge) : 0;
-        ff_n = kNegInf;
+      if (!kLocal && p == 0) {      // the top border H(0, j) and the F it
+        fh_n = V == kVarGlobal ? -gapw(jf + 1, go, ge) : 0;   // feeds into row 1,
+        ff_n = fh_n - go;           // max(F(0, j) - ge, H(0, j) - go)
       }
       if (p > 0 && jf < n) {
         const int2 v = rb[jf];

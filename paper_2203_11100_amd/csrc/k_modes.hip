@@ -123,8 +123,10 @@ __global__ __launch_bounds__(256) void k_mode_inter(ModeArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         if (first) {
+          // the top border H(0, j) and the F it feeds into row 1:
+          // max(F(0, j) - ge, H(0, j) - go) = H(0, j) - go
           const int top = MODE == SW_MODE_GLOBAL ? -gapw(j0 + q + 1, go, ge) : 0;
-          u[q] = make_int2(top, kNegInf);
+          u[q] = make_int2(top, top - go);
         } else {
           u[q] = rb[(size_t)(j0 + q) * 128];
         }
