@@ -480,20 +480,22 @@ def batched_leg(db, scale, replays=3):
                     "mean of %d replays" % len(times)}
 
 
-def served_leg(db, scale, n_requests, qps, slots=4, max_batch=8):
+def served_leg(db, scale, n_requests, qps, slots=4, max_batch=8, timeout_s=None):
     import numpy as np
     import swinputs
     from paper_2203_11100_amd import serve
     ws = swinputs.config("served", scale=scale, n_requests=n_requests, qps=qps)
     srv = serve.Server(db, ws.matrix, ws.gap_open, ws.gap_extend, max_slots=slots,
-                       max_batch=max_batch, max_query_len=5000)
-    srv.ex.warm()
+                       max_batch=max_batch, request_timeout=timeout_s)
+    srv.ex.warm(5000)
     log("served: %d requests at %.0f QPS on %d slots ..." % (n_requests, qps, srv.n_slots))
     reqs = srv.run(ws.queries, ws.arrivals)
     srv.close()
     s = serve.summarize(reqs, ws.n_residues)
     log("served: %s" % s)
     s.update({"qps": qps, "slots": srv.n_slots, "max_batch": max_batch, "unit_latency": "ms",
+              "request_memory_bytes": srv.request_memory, "peak_request_bytes": srv.peak_bytes,
+              "timeout_s": timeout_s,
               "arrivals": "Poisson, query lengths log-normal (median 400, sigma 0.8, "
                           "clip 30..5000)"})
     return s
@@ -505,8 +507,8 @@ def served_sweep(db, scale, n_requests, qps_points=(10, 25, 75), saturate=400.0)
     out = []
     for qps in list(qps_points) + [saturate]:
         s = served_leg(db, scale, n_requests, qps)
-        out.append({k: s[k] for k in ("qps", "requests", "p50_ms", "p99_ms", "gcups",
-                                      "mean_batch", "slots")})
+        out.append({k: s.get(k) for k in ("qps", "requests", "served", "p50_ms", "p99_ms",
+                                          "gcups", "mean_batch", "slots")})
     return out
 
 
