@@ -303,6 +303,11 @@ typedef struct sw_stats {
   int64_t intra_cells;     /* real cells given to the intra-task kernel */
   int32_t rows;            /* strip height of the last inter-task launch */
   int32_t waves;           /* waves per workgroup of the last inter-task launch */
+  int32_t long_items;      /* work items of the last single search's long-list
+                              kernel: pairs of long sequences, or (short
+                              queries) column segments of those pairs */
+  int32_t long_overlap;    /* columns each segment's window reaches back
+                              (-1: the pairs were not cut into segments) */
 } sw_stats;
 
 /* Waits for the recorded work, fills *out and resets the counters. */

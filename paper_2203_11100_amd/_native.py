@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("ms_intra", ctypes.c_float), ("ms_rescore", ctypes.c_float),
                 ("n_inter_launches", ctypes.c_int32), ("n_rescored", ctypes.c_int32),
                 ("inter_cells", ctypes.c_int64), ("intra_cells", ctypes.c_int64),
-                ("rows", ctypes.c_int32), ("waves", ctypes.c_int32)]
+                ("rows", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("long_items", ctypes.c_int32), ("long_overlap", ctypes.c_int32)]
 
 
 class HybridStats(ctypes.Structure):

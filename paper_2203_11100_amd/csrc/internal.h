@@ -138,6 +138,14 @@ struct IntraPairArgs {
   int32_t* out;
   int32_t* flag_count;        // rescoring list: count, then {sid, query}
   int2* flag_list;
+  // column segments (short queries): with seg_items non-null, item x is
+  // {pair, segment}; segment s of a pair covers columns [s*seg_cols,
+  // (s+1)*seg_cols) of its longer sequence and is computed over the window
+  // that starts seg_overlap columns earlier, with a zero left border; the
+  // item's packed maximum goes to seg_best[x] instead of `out`
+  const int2* seg_items;
+  int32_t seg_cols, seg_overlap;
+  uint32_t* seg_best;
 };
 
 // Batched inter-task kernel: the two 16-bit halves of a lane hold two
@@ -197,6 +205,11 @@ hipError_t launch_inter(int R, int W, int n_bins, const InterArgs& a, hipStream_
 hipError_t launch_intra(int RR, int W2, int grid, const IntraArgs& a, hipStream_t s);
 // R in {2, 4, 8}, W2 in {1, 2, 4, 8}, not (8, 8) (LDS)
 hipError_t launch_intra_pairs(int R, int W2, int grid, const IntraPairArgs& a, hipStream_t s);
+// Scores of segmented pairs: pair p's maximum over seg_best[seg0[p] ..
+// seg0[p+1]), written to out (or the rescoring list) per half.
+hipError_t launch_long_combine(const int2* pairs, const int32_t* seg0, int32_t n_pairs,
+                               const uint32_t* seg_best, int32_t sat_limit, int32_t* out,
+                               int32_t* flag_count, int2* flag_list, hipStream_t s);
 hipError_t launch_batch(int R, int W, int grid, const BatchArgs& a, hipStream_t s);
 int batch_workgroups_per_cu(int R, int W);
 hipError_t launch_mode_profile(const uint8_t* d_query, int m, const Matrix& mat, int R,

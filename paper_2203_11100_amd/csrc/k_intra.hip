@@ -34,6 +34,20 @@
 // before a lane's first column and after the sequence's end see the pad code,
 // whose profile score is <= 0, so they never raise the maximum.
 //
+// Column segments (packed kernel, short queries).  One long sequence's
+// wavefront takes about n steps however few rows the query has, so for a
+// short query the longest database sequence would set the search's time.
+// The packed kernel can instead take items {pair, segment}: segment s
+// covers columns [s*C, (s+1)*C) and is computed over a window starting
+// `overlap` columns earlier, from a zero left border, as an independent
+// local alignment of that window.  Every value computed there is a lower
+// bound of the true one (fewer alignments are possible), and it is exact in
+// the segment's own columns when every alignment of positive score ending
+// there starts inside the window, which the host guarantees by the span
+// bound at seg_overlap (runtime.hip).  The segments' maxima are combined per
+// pair afterwards (k_long_combine), so segments of one sequence run on
+// different workgroups at once.
+//
 // Each wave stages its pass's profile in LDS as int8 [code][row]: a lane
 // reads its R rows for its own residue code, R contiguous bytes at
 // code*64R + R*l, so the 64 reads of a wave cover consecutive bytes of one
@@ -359,15 +373,28 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
   const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
 
   for (int it = blockIdx.x; it < a.count; it += gridDim.x) {
-    const int2 item = a.items[it];
+    const int2 seg = a.seg_items ? a.seg_items[it] : make_int2(it, 0);
+    const int2 item = a.items[seg.x];
     const int sa = item.x, sb = item.y;
     const int64_t ba = a.offs[sa];
-    const int na = (int)(a.offs[sa + 1] - ba);
+    int na = (int)(a.offs[sa + 1] - ba);
     const int64_t bb = sb >= 0 ? a.offs[sb] : 0;
-    const int nb = sb >= 0 ? (int)(a.offs[sb + 1] - bb) : 0;
-    const int n = na > nb ? na : nb;
+    int nb = sb >= 0 ? (int)(a.offs[sb + 1] - bb) : 0;
     const uint8_t* __restrict__ sqa = a.res + ba;
     const uint8_t* __restrict__ sqb = a.res + bb;
+    if (a.seg_items) {
+      // the segment's window: columns [c0, hi) of both sequences, each cut
+      // to its own length (a is the longer one, so na stays >= 1); an empty
+      // b points at a's residues so that its clamped reads stay in bounds
+      const int lo = seg.y * a.seg_cols;
+      const int hi = min(na, lo + a.seg_cols);
+      const int c0 = max(0, lo - a.seg_overlap);
+      na = hi - c0;
+      nb = max(0, min(nb, hi) - c0);
+      sqa += c0;
+      sqb = nb > 0 ? sqb + c0 : sqa;
+    }
+    const int n = na > nb ? na : nb;
     const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
     const int T_total = q_last * C2 + kSkew * w_last + C2;
 
@@ -481,7 +508,12 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
     for (int off = 32; off > 0; off >>= 1) best = hmax2(best, (uint32_t)__shfl_xor((int)best, off, 64));
     if (lane == 0) lbest[w] = best;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && a.seg_best) {
+      uint32_t b = lbest[0];
+#pragma unroll
+      for (int x = 1; x < W2; ++x) b = hmax2(b, lbest[x]);
+      a.seg_best[it] = b;
+    } else if (threadIdx.x == 0) {
       uint32_t b = lbest[0];
 #pragma unroll
       for (int x = 1; x < W2; ++x) b = hmax2(b, lbest[x]);
@@ -499,6 +531,33 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
       }
     }
     __syncthreads();
+  }
+}
+
+// The score of each segmented pair: the maximum over its segments' packed
+// maxima (each a lower bound of the pair's scores, and the segment holding a
+// sequence's best cell computes that cell exactly), then per half the score
+// or, at the rescoring limit, an entry of the rescoring list.
+__global__ void k_long_combine(const int2* __restrict__ pairs, const int32_t* __restrict__ seg0,
+                               int32_t n_pairs, const uint32_t* __restrict__ seg_best,
+                               int32_t sat_limit, int32_t* __restrict__ out,
+                               int32_t* flag_count, int2* __restrict__ flag_list) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_pairs) return;
+  uint32_t b = 0;
+  for (int x = seg0[p]; x < seg0[p + 1]; ++x) b = hmax2(b, seg_best[x]);
+  const int2 item = pairs[p];
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    const int sid = half ? item.y : item.x;
+    if (sid < 0) continue;
+    const int score = half_score(b, half, sat_limit);
+    if (score < 0) {
+      const int idx = atomicAdd(flag_count, 1);
+      flag_list[idx] = make_int2(sid, 0);
+    } else {
+      out[sid] = score;
+    }
   }
 }
 
@@ -533,6 +592,15 @@ hipError_t launch_intra(int R, int W2, int grid, const IntraArgs& a, hipStream_t
   SWDB_CASE(2, 8) SWDB_CASE(4, 8) SWDB_CASE(8, 8)
 #undef SWDB_CASE
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_long_combine(const int2* pairs, const int32_t* seg0, int32_t n_pairs,
+                               const uint32_t* seg_best, int32_t sat_limit, int32_t* out,
+                               int32_t* flag_count, int2* flag_list, hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_long_combine, dim3((n_pairs + 255) / 256), dim3(256), 0, s, pairs, seg0,
+                     n_pairs, seg_best, sat_limit, out, flag_count, flag_list);
+  return hipGetLastError();
 }
 
 hipError_t launch_intra_pairs(int R, int W2, int grid, const IntraPairArgs& a, hipStream_t s) {

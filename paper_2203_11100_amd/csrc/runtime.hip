@@ -163,6 +163,14 @@ struct DbData {
   DevBuf<int2> d_long_items;        // {sid, 0} for the long list
   DevBuf<int2> d_long_pairs;        // {sid a, sid b or -1}: the long list in pairs
   int64_t n_long_pairs = 0;
+  // column segments of the long pairs for short queries: seg_cols columns
+  // each, items {pair, segment} pair by pair, pair p's items from
+  // d_pair_seg0[p]; any_split when some pair has more than one
+  int32_t seg_cols = 0;
+  int64_t n_seg_items = 0;
+  bool any_split = false;
+  DevBuf<int2> d_seg_items;
+  DevBuf<int32_t> d_pair_seg0;
   // host copies for the hybrid search's CPU share: residues, offsets, bin
   // descriptors {res_off, rb_off, len, slot0} and slots
   std::vector<uint8_t> h_res;
@@ -179,6 +187,7 @@ struct Searcher {
   DevBuf<int2> rb_long;             // intra-task boundary rows, per workgroup
   DevBuf<int2> rb_resc;
   DevBuf<int32_t> flags;            // [0] count, [2..] {sid, query} rescoring list
+  DevBuf<uint32_t> seg_best;        // packed maximum of every long-pair segment item
   DevBuf<uint32_t> prof;            // per-query buffers, grown on demand
   DevBuf<int8_t> prof2;
   DevBuf<uint32_t> prof3;           // binary16 row pairs of the packed intra-task kernel
@@ -233,6 +242,7 @@ void release_searcher(Searcher* db) {
   if (db->own_stream) (void)hipStreamSynchronize(db->own_stream);
   if (db->aux_stream) (void)hipStreamSynchronize(db->aux_stream);
   db->rb.release(); db->rb_long.release(); db->rb_resc.release(); db->flags.release();
+  db->seg_best.release();
   db->prof.release(); db->prof2.release(); db->prof3.release(); db->q_stage.release();
   db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
@@ -261,13 +271,15 @@ void destroy_db(sw_db* h) {
   d.packed.release(); d.bins.release(); d.slot_seq.release(); d.res.release(); d.offs.release();
   d.d_long_items.release();
   d.d_long_pairs.release();
+  d.d_seg_items.release();
+  d.d_pair_seg0.release();
   delete h;
 }
 
 // Makes every buffer of a searcher wait for its streams before reallocation.
 void bind_buffers(Searcher* S) {
   const StreamSet* u = &S->users;
-  S->rb.users = S->rb_long.users = S->rb_resc.users = u;
+  S->rb.users = S->rb_long.users = S->rb_resc.users = S->seg_best.users = u;
   S->prof.users = u; S->prof2.users = u; S->prof3.users = u; S->q_stage.users = u;
   S->out_stage.users = u;
   S->rb_batch.users = S->counter.users = S->flags.users = u;
@@ -295,7 +307,8 @@ int init_searcher(Searcher* S, DbData* d) {
           hipSuccess ||
       (e = S->flags.reserve(
            (size_t)(2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)))) !=
-          hipSuccess)
+          hipSuccess ||
+      (e = S->seg_best.reserve((size_t)std::max<int64_t>(d->n_seg_items, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("search scratch: ") + hipGetErrorString(e));
   // the inter-task kernel's first strip reads zeros from the boundary rows;
   // every search leaves them zeroed again
@@ -494,6 +507,32 @@ int32_t effective_limit(int32_t requested) {
 // largest pass (64 lanes x 8 rows), so every (R, W2) can read them.
 int intra_rows_pad(int m) { return (m + 511) / 512 * 512; }
 
+// Boundary-row length one workgroup of the long-pair kernel needs for a
+// column segment: a window is at most a segment plus an overlap no longer
+// than a segment.
+int64_t seg_stride(const DbData& d) {
+  return std::max<int64_t>(1, std::min<int64_t>(d.plan.max_long_len, 2 * (int64_t)d.seg_cols));
+}
+
+// Columns a segment's window reaches back for a query of length m, or -1
+// when the long pairs are not cut into segments for it.  A local alignment
+// of positive score pairs r <= m residues of each sequence, gaining at most
+// r * maxS, and every database column it skips costs at least gap_extend
+// (a gap of k costs open + (k-1) extend >= k extend), so it skips fewer
+// than r * maxS / extend columns and spans fewer than m + m * maxS / extend.
+// A window starting that far before its segment therefore holds every
+// positive-score alignment that ends in the segment, and the recurrence
+// started there with a zero border gives exactly the true H in the
+// segment's columns (lower bounds elsewhere).  Used when this reach is at
+// most one segment (short queries) and extend > 0.
+int32_t seg_overlap(const DbData& d, int m, const Matrix& mat, int32_t ge) {
+  if (!d.any_split || ge <= 0) return -1;
+  int max_s = 0;
+  for (int x = 0; x < SW_ALPHA * SW_ALPHA; ++x) max_s = std::max<int>(max_s, mat.v[x]);
+  const int64_t reach = (int64_t)m + ((int64_t)m * max_s + ge - 1) / ge;
+  return reach <= d.seg_cols ? (int32_t)reach : -1;
+}
+
 // Schedule of one single-query search: inter-task strips (R rows, W waves),
 // the packed long-sequence kernel (RR, W2), the rescoring kernel (RRr, W2r)
 // and the intra-task profiles' row length.
@@ -525,7 +564,9 @@ struct SearchScratch {
   int8_t* prof2 = nullptr;    // intra-task int8 profile
   uint32_t* prof3 = nullptr;  // packed intra-task profile (long list present)
   int2* rb_long = nullptr;    // per-workgroup rows of the long-sequence kernel
-  int grid_long = 0;
+  int grid_long = 0;          // its workgroups over whole pairs
+  int grid_seg = 0;           // and over column segments (rows of seg_stride)
+  uint32_t* seg_best = nullptr;   // segment maxima (long list present)
   int2* rb_resc = nullptr;    // per-workgroup rows of the rescoring kernel
   int grid_resc = 0;
 };
@@ -569,7 +610,11 @@ int reserve_search_scratch(Searcher* db, const SearchShape& sh, SearchScratch* X
   if (n_long > 0 && (e = db->prof3.reserve((size_t)kIntraCodes * (sh.m_pad2 / 2))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
   const int grid_long = (int)std::min<int64_t>(db->d->n_long_pairs, kIntraGridLong);
-  if (n_long > 0 && (e = reserve_long_scratch(db, grid_long)) != hipSuccess)
+  const int grid_seg = (int)std::min<int64_t>(db->d->n_seg_items, kIntraGridLong);
+  if (n_long > 0 && (e = db->rb_long.reserve(std::max<size_t>(
+                         {(size_t)std::max(grid_long, 1) * (size_t)std::max<int32_t>(
+                                                               db->d->plan.max_long_len, 1),
+                          (size_t)grid_seg * (size_t)seg_stride(*db->d), 1}))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
   X->rb = db->rb.p;
   X->flags = db->flags.p;
@@ -578,6 +623,8 @@ int reserve_search_scratch(Searcher* db, const SearchShape& sh, SearchScratch* X
   X->prof3 = n_long > 0 ? db->prof3.p : nullptr;
   X->rb_long = db->rb_long.p;
   X->grid_long = grid_long;
+  X->grid_seg = grid_seg;
+  X->seg_best = n_long > 0 ? db->seg_best.p : nullptr;
   X->rb_resc = db->rb_resc.p;
   X->grid_resc = kIntraGridRescore;
   return SW_OK;
@@ -647,9 +694,29 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
     la.out = d_out;
     la.flag_count = X.flags;
     la.flag_list = flist;
+    int grid = X.grid_long;
+    // short queries: the long pairs in column segments (seg_overlap)
+    const int32_t overlap = seg_overlap(*db->d, m, mat, ge);
+    const bool segmented = overlap >= 0 && X.seg_best && X.grid_seg > 0;
+    if (segmented) {
+      la.seg_items = db->d->d_seg_items.p;
+      la.count = (int32_t)db->d->n_seg_items;
+      la.seg_cols = db->d->seg_cols;
+      la.seg_overlap = overlap;
+      la.seg_best = X.seg_best;
+      la.scratch_stride = seg_stride(*db->d);
+      grid = X.grid_seg;
+    }
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
     if ((e = launch_intra_pairs(RR, W2, X.grid_long, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
+    db->stats.long_items = la.count;
+    db->stats.long_overlap = segmented ? overlap : -1;
+    if (segmented &&
+        (e = launch_long_combine(db->d->d_long_pairs.p, db->d->d_pair_seg0.p,
+                                 (int32_t)db->d->n_long_pairs, X.seg_best, la.sat_limit, d_out,
+                                 X.flags, flist, db->aux_stream)) != hipSuccess)
+      return hip_fail(e, "segment maxima");
     time_end(db, tl, db->aux_stream);
     if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "event");
@@ -1212,6 +1279,21 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   for (size_t t = 0; t < h_long_pairs.size(); ++t)
     h_long_pairs[t] = make_int2(h_long[2 * t], 2 * t + 1 < h_long.size() ? h_long[2 * t + 1] : -1);
   d->n_long_pairs = (int64_t)h_long_pairs.size();
+  // column segments of twice the long threshold (the longer sequence of a
+  // pair sets its count)
+  d->seg_cols = (int32_t)std::min<int64_t>(std::max<int64_t>(64, 2 * (int64_t)P.long_threshold),
+                                           SW_MAX_LEN);
+  std::vector<int2> h_seg_items;
+  std::vector<int32_t> h_pair_seg0(h_long_pairs.size() + 1, 0);
+  for (size_t p = 0; p < h_long_pairs.size(); ++p) {
+    h_pair_seg0[p] = (int32_t)h_seg_items.size();
+    const int64_t n_p = d->long_len[(size_t)h_long_pairs[p].x];
+    const int64_t k_p = std::max<int64_t>(1, (n_p + d->seg_cols - 1) / d->seg_cols);
+    if (k_p > 1) d->any_split = true;
+    for (int64_t x = 0; x < k_p; ++x) h_seg_items.push_back(make_int2((int)p, (int)x));
+  }
+  h_pair_seg0[h_long_pairs.size()] = (int32_t)h_seg_items.size();
+  d->n_seg_items = (int64_t)h_seg_items.size();
 
   auto alloc_fail = [&](hipError_t err, const char* what) {
     destroy_db(h);
@@ -1226,6 +1308,9 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   if ((e = d->d_long_items.reserve((size_t)P.n_long)) != hipSuccess) return alloc_fail(e, "long ids");
   if ((e = d->d_long_pairs.reserve(h_long_pairs.size())) != hipSuccess)
     return alloc_fail(e, "long pairs");
+  if ((e = d->d_seg_items.reserve(h_seg_items.size())) != hipSuccess ||
+      (e = d->d_pair_seg0.reserve(h_pair_seg0.size())) != hipSuccess)
+    return alloc_fail(e, "long segments");
   auto up = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
     return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
@@ -1236,7 +1321,9 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
       (e = up(d->res.p, residues, (size_t)d->n_res)) != hipSuccess ||
       (e = up(d->offs.p, offsets, ((size_t)n_seqs + 1) * 8)) != hipSuccess ||
       (e = up(d->d_long_items.p, h_long_items.data(), h_long_items.size() * 8)) != hipSuccess ||
-      (e = up(d->d_long_pairs.p, h_long_pairs.data(), h_long_pairs.size() * 8)) != hipSuccess) {
+      (e = up(d->d_long_pairs.p, h_long_pairs.data(), h_long_pairs.size() * 8)) != hipSuccess ||
+      (e = up(d->d_seg_items.p, h_seg_items.data(), h_seg_items.size() * 8)) != hipSuccess ||
+      (e = up(d->d_pair_seg0.p, h_pair_seg0.data(), h_pair_seg0.size() * 4)) != hipSuccess) {
     destroy_db(h);
     return hip_fail(e, "database upload");
   }
@@ -2081,7 +2168,8 @@ int64_t sw_ctx_bytes(const sw_db* h) {
   if (!h) return -1;
   const swdb::Plan& P = h->data.plan;
   return P.boundary_uint4 * 16 + (int64_t)swdb::kIntraGridRescore * swdb::rescore_stride(P) * 8 +
-         (2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)) * 4;
+         (2 + 2 * std::max<int64_t>(P.n_bins * SW_BIN_SEQS + P.n_long, 1)) * 4 +
+         std::max<int64_t>(h->data.n_seg_items, 1) * 4;
 }
 
 int sw_ctx_search_async(sw_ctx* c, const uint8_t* d_query, int32_t query_len,

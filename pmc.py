@@ -4,13 +4,15 @@ Runs, in one process:
   1. a plain device-to-device copy of COPY_MIB MiB (torch), the calibration
      kernel of known traffic: COPY_MIB MiB read and COPY_MIB MiB written;
   2. the plain benchmark workload's searches for the chosen queries (default:
-     all 20), with the database already resident.
+     all 20), with the database already resident; with --long-only, the same
+     queries against a database of only the plain database's long sequences
+     (2,048 residues or more), so the long-sequence kernel runs alone.
 
 Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
 block per run) each dispatch gets its counter value; dividing a search
 kernel's value by the copy kernel's value per MiB converts it into bytes.
 
-    python pmc.py [--queries 0,19] [--copy-mib 1024]
+    python pmc.py [--queries 0,19] [--copy-mib 1024] [--long-only] [--repeat N]
 """
 import argparse
 import json
@@ -28,6 +30,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--queries", default="all")
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
+    ap.add_argument("--long-only", action="store_true")
+    ap.add_argument("--repeat", type=int, default=1)
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -42,17 +46,29 @@ def main():
     del a, b
     w = swinputs.config("plain")
     idx = range(len(w.queries)) if args.queries == "all" else [int(x) for x in args.queries.split(",")]
-    with sw.Database(w.residues, w.offsets) as db:
+    res, offs = w.residues, w.offsets
+    if args.long_only:
+        lens = np.diff(offs)
+        keep = np.nonzero(lens >= sw.SW_DEFAULT_LONG_THRESHOLD)[0]
+        res = np.concatenate([res[offs[i]:offs[i + 1]] for i in keep])
+        offs = np.zeros(len(keep) + 1, np.int64)
+        np.cumsum(lens[keep], out=offs[1:])
+    with sw.Database(res, offs) as db:
         out = torch.empty(db.n_seqs, dtype=torch.int32, device="cuda")
         info = []
-        for i in idx:
-            q = torch.from_numpy(w.queries[i]).cuda()
-            db.search_async(q, w.matrix, w.gap_open, w.gap_extend, out)
-            torch.cuda.synchronize()
-            st = db.stats()
-            info.append({"query": i, "m": len(w.queries[i]), "inter_cells": st["inter_cells"],
-                         "rows": st["rows"], "waves": st["waves"]})
-    print(json.dumps({"copy_mib": args.copy_mib, "searches": info}), flush=True)
+        for _ in range(args.repeat):
+            for i in idx:
+                q = torch.from_numpy(w.queries[i]).cuda()
+                db.search_async(q, w.matrix, w.gap_open, w.gap_extend, out)
+                torch.cuda.synchronize()
+                st = db.stats()
+                info.append({"query": i, "m": len(w.queries[i]), "inter_cells": st["inter_cells"],
+                             "intra_cells": st["intra_cells"], "long_items": st["long_items"],
+                             "long_overlap": st["long_overlap"], "rows": st["rows"],
+                             "waves": st["waves"]})
+    print(json.dumps({"copy_mib": args.copy_mib, "long_only": args.long_only,
+                      "n_seqs": int(len(offs) - 1), "n_residues": int(offs[-1]),
+                      "searches": info}), flush=True)
 
 
 if __name__ == "__main__":

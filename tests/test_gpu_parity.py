@@ -145,6 +145,52 @@ def test_intra_task_path(sw, intra_rows, intra_waves, t_long):
     assert (got == _oracle(q, res, offs)).all()
 
 
+def _segment_db(seed=12):
+    """Long sequences of 500..20,000 residues (lengths at and around
+    multiples of 1,000, the segment length for long threshold 500) among
+    short ones, one of them an embedded copy target."""
+    rng = np.random.default_rng(seed)
+    lengths = np.concatenate([rng.integers(20, 499, 300), [500, 999, 1000, 1001, 1999, 2000,
+                                                           2001, 3000, 20_000, 12_345],
+                              rng.integers(500, 9_000, 40)]).astype(np.int64)
+    rng.shuffle(lengths)
+    return swinputs.make_database(lengths, rng)
+
+
+@pytest.mark.parametrize("m,go,ge,segmented", [(1, 10, 2, True), (10, 10, 2, True),
+                                                (60, 10, 2, True), (150, 10, 2, True),
+                                                (160, 10, 2, False), (83, 10, 1, True),
+                                                (84, 12, 1, False), (40, 5, 0, False),
+                                                (100, 40, 20, True)])
+def test_long_pairs_in_column_segments(sw, m, go, ge, segmented):
+    """Short queries score the long pairs in column segments of 1,000
+    columns (twice the long threshold) whose windows reach back
+    m + ceil(11 m / extend) columns; scores stay exact, including segment
+    boundaries, planted copies and every sequence sent to rescoring."""
+    res, offs = _segment_db()
+    rng = np.random.default_rng(m)
+    q = swinputs.random_residues(m, rng)
+    # plant the query across a segment boundary of the 20,000-residue sequence
+    lens = np.diff(offs)
+    big = int(np.nonzero(lens == 20_000)[0][0])
+    at = int(offs[big]) + 4_000 - m // 2
+    res = res.copy()
+    res[at:at + m] = q
+    reach = m + (m * 11 + ge - 1) // ge if ge > 0 else None
+    say("segments: m=%d gaps %d/%d reach %s" % (m, go, ge, reach))
+    want = _oracle(q, res, offs, go=go, ge=ge)
+    with sw.Database(res, offs, long_threshold=500) as db:
+        for limit in (32767, 40):
+            db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
+            got = db.search(q, B62, go, ge)
+            st = db.stats()
+            assert (got == want).all(), np.nonzero(got != want)[0][:10]
+            assert (st["long_overlap"] == reach) if segmented else (st["long_overlap"] == -1)
+            n_pairs = (db.info()["n_long"] + 1) // 2
+            assert (st["long_items"] > n_pairs) if segmented else (st["long_items"] == n_pairs)
+    assert want[big] == sum(int(B62[c, c]) for c in q)
+
+
 @pytest.mark.parametrize("limit", [0, 40, 32767])
 def test_forced_rescoring(sw, limit):
     res, offs = _ragged_db(3)
