@@ -449,8 +449,10 @@ def long_mix_leg(scale, steps=2):
 
 
 def batched_leg(db, scale, replays=3):
-    """220 queries in one batched search; first call plans and captures the
-    graph (untimed), then the mean of `replays` timed replays."""
+    """220 queries in one batched search, first with the schedule fitted to
+    the pairs, then with the one the autotuner picks for these query
+    lengths; each form's first call plans and captures the graph (untimed),
+    then the mean of `replays` timed replays."""
     import numpy as np
     import torch
     import swinputs
@@ -461,23 +463,41 @@ def batched_leg(db, scale, replays=3):
     qoffs = np.zeros(len(wb.queries) + 1, np.int64)
     np.cumsum([len(q) for q in wb.queries], out=qoffs[1:])
     out = torch.empty((len(wb.queries), db.n_seqs), dtype=torch.int32, device="cuda")
-    db.search_batch_async(cat, qoffs, wb.matrix, wb.gap_open, wb.gap_extend, out)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(max(1, replays)):
-        t0 = time.perf_counter()
+
+    def timed():
         db.search_batch_async(cat, qoffs, wb.matrix, wb.gap_open, wb.gap_extend, out)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    dt = sum(times) / len(times)
+        times = []
+        for _ in range(max(1, replays)):
+            t0 = time.perf_counter()
+            db.search_batch_async(cat, qoffs, wb.matrix, wb.gap_open, wb.gap_extend, out)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        return sum(times) / len(times), times
+
+    dt_fit, times_fit = timed()
+    log("batched (fitted): %.3f s, %.0f GCUPS" % (dt_fit, cells / dt_fit / 1e9))
+    t0 = time.perf_counter()
+    rep = db.autotune([len(q) for q in wb.queries])
+    tune_s = time.perf_counter() - t0
+    dt, times = timed()
+    db.autotune([0])                  # back to the fitted schedules for the other legs
     db.stats()
     del out
-    log("batched: %.3f s mean of %d replays, %.0f GCUPS" % (dt, len(times), cells / dt / 1e9))
+    log("batched (autotuned in %.1f s): %.3f s mean of %d replays, %.0f GCUPS"
+        % (tune_s, dt, len(times), cells / dt / 1e9))
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "ms_per_step": dt * 1e3,
             "replays_ms": [t * 1e3 for t in times],
+            "fitted": {"value": cells / dt_fit / 1e9, "ms_per_step": dt_fit * 1e3,
+                       "replays_ms": [t * 1e3 for t in times_fit]},
+            "autotune": {"seconds": tune_s,
+                         "buckets": [{"query_len": b["query_len"], "batch_chosen": b["batch_chosen"],
+                                      "batch_gcups": b["batch_gcups"]}
+                                     for b in rep["buckets"]]},
             "n_queries": len(wb.queries), "cells_per_step": cells,
-            "form": "one batched search (paired queries, persistent kernel, HIP graph replay), "
-                    "mean of %d replays" % len(times)}
+            "form": "one batched search (paired queries, persistent kernel, HIP graph replay) "
+                    "with the autotuned schedule, mean of %d replays; `fitted` is the same with "
+                    "the schedule fitted to the pairs" % len(times)}
 
 
 def served_leg(db, scale, n_requests, qps, slots=4, max_batch=8, timeout_s=None):

@@ -313,30 +313,59 @@ typedef struct sw_stats {
 /* Waits for the recorded work, fills *out and resets the counters. */
 int sw_get_stats(sw_db* db, sw_stats* out);
 
-/* sw_autotune: chooses the inter-task schedules for this database by
- * measurement.  For each query-length bucket (m < 256, < 768, < 2048, longer)
- * it times every candidate (rows, waves) of the single-query kernel on one
- * random query of a representative length (192, 448, 1280, 4096 residues),
- * and of the batched kernel on one pair of such queries, with HIP events
- * around the kernels, and keeps the candidate with the highest GCUPS.
+/* sw_autotune: chooses the schedules of this database's searches by
+ * measurement (the paper finds the GCUPS sensitive to the work-group size and
+ * the best size different from SW#db's default, section 4.2).  Query lengths
+ * fall in four buckets (m < 256, < 768, < 2048, longer); for each bucket it
+ * searches one random query of a representative length and, with HIP events
+ * around the kernels, times
+ *  - every inter-task schedule (rows, waves) of the single-query kernel: the
+ *    fitted choice (0, 0) and the seven forms 20/18/16/14/12 x 12 and
+ *    14/12 x 16 (SW_TUNE_CANDIDATES), keeping the highest GCUPS;
+ *  - the same schedules of the batched kernel on a pair of such queries;
+ *  - every (rows per lane, waves) of the long-sequence kernel of single
+ *    searches (SW_TUNE_INTRA_CANDIDATES, when the database has long
+ *    sequences), keeping the shortest kernel time.
  * Later searches on the handle (and contexts created afterwards) use the
- * tuned entry of their query's bucket unless SW_OPT_ROWS / SW_OPT_WAVES are
- * set.  The candidate (0, 0) is the schedule fitted to the query lengths
- * (each query's in single searches, the pairs' in batched ones).  Takes
- * about a second on a 200,000-sequence database.  `report` may be NULL.
- * Errors leave the handle untuned. */
+ * tuned entries of their query's bucket unless SW_OPT_ROWS / SW_OPT_WAVES /
+ * SW_OPT_INTRA_ROWS / SW_OPT_INTRA_WAVES are set.  sw_autotune uses the
+ * representative lengths 192, 448, 1280 and 4096 and takes a few seconds on
+ * a 200,000-sequence database.  `report` may be NULL.  Errors leave the
+ * handle untuned.
+ *
+ * sw_autotune_ex tunes for the caller's workload and can persist the result:
+ *   query_lens : host, int32_t[n_lens], the lengths the caller will search
+ *                (NULL / 0: the default lengths); a bucket's representative
+ *                length is the median of the lengths in it, and buckets with
+ *                none stay untuned (fitted schedules) - lengths that are all
+ *                0 measure nothing and clear an earlier tuning;
+ *   cache_path : NULL, or a text file of tuning results keyed by the GPU
+ *                architecture name, its compute-unit count, a digest of the
+ *                database's shape (sequence count, residues, long threshold,
+ *                histogram of log2 lengths) and the representative lengths.
+ *                A matching entry is applied without measuring (report
+ *                from_cache = 1); otherwise the measured result is appended.
+ *                An unreadable or unwritable file returns SW_EINVAL. */
 #define SW_TUNE_BUCKETS 4
-#define SW_TUNE_CANDIDATES 4
+#define SW_TUNE_CANDIDATES 8
+#define SW_TUNE_INTRA_CANDIDATES 11
 typedef struct sw_tune_report {
-  int32_t query_len[SW_TUNE_BUCKETS];            /* representative lengths */
-  int32_t cand_rows[SW_TUNE_CANDIDATES];         /* candidate schedules */
+  int32_t query_len[SW_TUNE_BUCKETS];            /* representative lengths (0: untuned) */
+  int32_t cand_rows[SW_TUNE_CANDIDATES];         /* inter-task candidates ((0, 0) fitted) */
   int32_t cand_waves[SW_TUNE_CANDIDATES];
   float gcups[SW_TUNE_BUCKETS][SW_TUNE_CANDIDATES];        /* single-query kernel */
   float batch_gcups[SW_TUNE_BUCKETS][SW_TUNE_CANDIDATES];  /* batched kernel */
   int32_t rows[SW_TUNE_BUCKETS], waves[SW_TUNE_BUCKETS];   /* chosen */
   int32_t batch_rows[SW_TUNE_BUCKETS], batch_waves[SW_TUNE_BUCKETS];
+  int32_t intra_cand_rows[SW_TUNE_INTRA_CANDIDATES];       /* long-sequence candidates */
+  int32_t intra_cand_waves[SW_TUNE_INTRA_CANDIDATES];
+  float intra_ms[SW_TUNE_BUCKETS][SW_TUNE_INTRA_CANDIDATES];  /* its kernel time, ms */
+  int32_t intra_rows[SW_TUNE_BUCKETS], intra_waves[SW_TUNE_BUCKETS];  /* chosen (0: none) */
+  int32_t from_cache;                            /* 1: applied from cache_path */
 } sw_tune_report;
 int sw_autotune(sw_db* db, sw_tune_report* report);
+int sw_autotune_ex(sw_db* db, const int32_t* query_lens, int32_t n_lens, const char* cache_path,
+                   sw_tune_report* report);
 
 /* ----------------------------------------------------------- search contexts
  * A database handle carries one search context; sw_ctx_create adds more, each

@@ -186,12 +186,17 @@ class Database:
         _native.check(_native.lib().sw_get_stats(self._h, ctypes.byref(st)))
         return {k: getattr(st, k) for k, _ in _native.Stats._fields_}
 
-    def autotune(self) -> dict:
-        """Measures the candidate schedules on this database (sw_autotune) and
-        returns the report; later searches use the chosen ones."""
+    def autotune(self, query_lens=None, cache: Optional[str] = None) -> dict:
+        """Measures the candidate schedules on this database (sw_autotune_ex)
+        for the given query lengths (None: the library's default lengths),
+        reading or appending the tuning cache file `cache` if given; returns
+        the report.  Later searches use the chosen schedules."""
         rep = _native.TuneReport()
-        _native.check(_native.lib().sw_autotune(self._h, ctypes.byref(rep)))
-        nb, nc = _native.TUNE_BUCKETS, _native.TUNE_CANDIDATES
+        lens = None if query_lens is None else np.ascontiguousarray(query_lens, dtype=np.int32)
+        _native.check(_native.lib().sw_autotune_ex(
+            self._h, _ptr(lens), 0 if lens is None else len(lens),
+            None if cache is None else str(cache).encode(), ctypes.byref(rep)))
+        nb, nc, ni = _native.TUNE_BUCKETS, _native.TUNE_CANDIDATES, _native.TUNE_INTRA_CANDIDATES
         cands = [(rep.cand_rows[c], rep.cand_waves[c]) for c in range(nc)]
         out = []
         for b in range(nb):

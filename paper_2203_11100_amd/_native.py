@@ -58,7 +58,7 @@ class HybridStats(ctypes.Structure):
                 ("cpu_threads", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
-TUNE_BUCKETS, TUNE_CANDIDATES = 4, 4
+TUNE_BUCKETS, TUNE_CANDIDATES, TUNE_INTRA_CANDIDATES = 4, 8, 11
 
 
 class TuneReport(ctypes.Structure):
@@ -69,7 +69,13 @@ class TuneReport(ctypes.Structure):
                 ("batch_gcups", (ctypes.c_float * TUNE_CANDIDATES) * TUNE_BUCKETS),
                 ("rows", ctypes.c_int32 * TUNE_BUCKETS), ("waves", ctypes.c_int32 * TUNE_BUCKETS),
                 ("batch_rows", ctypes.c_int32 * TUNE_BUCKETS),
-                ("batch_waves", ctypes.c_int32 * TUNE_BUCKETS)]
+                ("batch_waves", ctypes.c_int32 * TUNE_BUCKETS),
+                ("intra_cand_rows", ctypes.c_int32 * TUNE_INTRA_CANDIDATES),
+                ("intra_cand_waves", ctypes.c_int32 * TUNE_INTRA_CANDIDATES),
+                ("intra_ms", (ctypes.c_float * TUNE_INTRA_CANDIDATES) * TUNE_BUCKETS),
+                ("intra_rows", ctypes.c_int32 * TUNE_BUCKETS),
+                ("intra_waves", ctypes.c_int32 * TUNE_BUCKETS),
+                ("from_cache", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/swdb.h declares
@@ -94,6 +100,7 @@ SIGNATURES = {
     "sw_set_option": (ctypes.c_int, [P, I32, I64]),
     "sw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(Stats)]),
     "sw_autotune": (ctypes.c_int, [P, ctypes.POINTER(TuneReport)]),
+    "sw_autotune_ex": (ctypes.c_int, [P, P, I32, ctypes.c_char_p, ctypes.POINTER(TuneReport)]),
     "sw_plan": (ctypes.c_int, [P, P, I64, I32, ctypes.POINTER(PlanInfo)]),
     "sw_ctx_create": (ctypes.c_int, [P, ctypes.POINTER(P)]),
     "sw_ctx_free": (None, [P]),

@@ -218,6 +218,8 @@ struct Searcher {
   // autotuned (rows, waves) per query-length bucket; 0 = not tuned
   int32_t tune_rows[SW_TUNE_BUCKETS] = {}, tune_waves[SW_TUNE_BUCKETS] = {};
   int32_t tune_brows[SW_TUNE_BUCKETS] = {}, tune_bwaves[SW_TUNE_BUCKETS] = {};
+  // autotuned (rows per lane, waves) of the long-pair kernel; 0 = not tuned
+  int32_t tune_irows[SW_TUNE_BUCKETS] = {}, tune_iwaves[SW_TUNE_BUCKETS] = {};
   sw_stats stats{};                 // since the last sw_get_stats
   std::mutex mtx;
 };
@@ -423,6 +425,14 @@ void pick_schedule(const Searcher* db, int m, int* R_out, int* W_out) {
 // (its LDS profile would exceed 160 KB).
 void pick_intra(const Searcher* db, int m, int max_waves, int* R_out, int* W2_out,
                 bool packed = false) {
+  if (packed && !db->opt_intra_rows && !db->opt_intra_waves) {
+    const int b = tune_bucket(m);
+    if (db->tune_iwaves[b]) {     // the autotuned entry of the query's bucket
+      *R_out = db->tune_irows[b];
+      *W2_out = db->tune_iwaves[b];
+      return;
+    }
+  }
   double best = 1e300;
   int bR = 8, bW = 1;
   for (int R : {2, 4, 8}) {
@@ -1874,29 +1884,158 @@ static int impl_get_stats(swdb::Searcher* db, sw_stats* out) {
 }
 
 // ---------------------------------------------------------------- autotuner
-// Times each candidate schedule of the single-query and batched inter-task
-// kernels on this database with one random query (or query pair) of a
-// representative length per bucket, and keeps the fastest per bucket.
-static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
+// Candidate schedules: the inter-task (rows, waves) forms ((0, 0) = fitted to
+// the query) and the long-pair kernel's (rows per lane, waves).
+static const int kTuneR[SW_TUNE_CANDIDATES] = {0, 20, 18, 16, 14, 12, 14, 12};
+static const int kTuneW[SW_TUNE_CANDIDATES] = {0, 12, 12, 12, 12, 12, 16, 16};
+static const int kTuneIR[SW_TUNE_INTRA_CANDIDATES] = {2, 4, 8, 2, 4, 8, 2, 4, 8, 2, 4};
+static const int kTuneIW[SW_TUNE_INTRA_CANDIDATES] = {1, 1, 1, 2, 2, 2, 4, 4, 4, 8, 8};
+
+// Key of a tuning-cache entry: GPU architecture, compute units, a digest of
+// the database's shape and the representative query lengths.
+static std::string tune_key(const swdb::Searcher* db, const int (&rep_len)[SW_TUNE_BUCKETS]) {
+  const swdb::DbData& d = *db->d;
+  char arch[256] = "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d.device) == hipSuccess) {
+    strncpy(arch, prop.gcnArchName, sizeof(arch) - 1);
+    arch[sizeof(arch) - 1] = 0;
+    for (char* c = arch; *c; ++c)
+      if (*c == ' ' || *c == '\t') *c = '_';
+  }
+  // FNV-1a over the shape: counts, threshold and the log2-length histogram
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int k = 0; k < 8; ++k) { h ^= (v >> (8 * k)) & 0xffu; h *= 1099511628211ull; }
+  };
+  int64_t hist[32] = {};
+  for (size_t i = 0; i + 1 < d.h_offs.size(); ++i) {
+    const int64_t len = d.h_offs[i + 1] - d.h_offs[i];
+    int lg = 0;
+    while (lg < 31 && (int64_t(1) << lg) <= len) ++lg;
+    ++hist[lg];
+  }
+  mix((uint64_t)d.n_seqs);
+  mix((uint64_t)d.n_res);
+  mix((uint64_t)d.plan.long_threshold);
+  for (int64_t v : hist) mix((uint64_t)v);
+  char buf[512];
+  snprintf(buf, sizeof(buf), "%s cus=%d db=%016llx lens=%d,%d,%d,%d", arch, d.n_cus,
+           (unsigned long long)h, rep_len[0], rep_len[1], rep_len[2], rep_len[3]);
+  return buf;
+}
+
+// Sums the recorded kernel times of one kind and recycles the events.
+static float drain_timed(swdb::Searcher* db, int kind) {
+  float total = 0;
+  for (auto& t : db->timed) {
+    (void)hipEventSynchronize(t.b);
+    float ms = 0;
+    if (t.kind == kind && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) total += ms;
+    db->ev_pool.push_back(t.a);
+    db->ev_pool.push_back(t.b);
+  }
+  db->timed.clear();
+  return total;
+}
+
+// Times each candidate schedule on this database with one random query (or
+// query pair) of a representative length per bucket, and keeps the best per
+// bucket; or applies a matching entry of the tuning cache.
+static int impl_autotune(swdb::Searcher* db, const int32_t* query_lens, int32_t n_lens,
+                         const char* cache_path, sw_tune_report* rep) {
   using namespace swdb;
   if (!db) return fail(SW_EINVAL, "db is NULL");
+  if (n_lens < 0 || (n_lens > 0 && !query_lens)) return fail(SW_EINVAL, "bad query lengths");
   std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
   if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
   DeviceGuard g(db->d->device);
-  if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) return SW_OK;
-  static const int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
-  // (0, 0): the fitted schedule of each query length (single queries),
-  // 16 rows and 12 waves (batched)
-  static const int cand_r[SW_TUNE_CANDIDATES] = {16, 0, 32, 32};
-  static const int cand_w[SW_TUNE_CANDIDATES] = {8, 0, 4, 8};
-  hipError_t e;
-  hipStream_t s = db->own_stream;
+  sw_tune_report local{};
+  for (int c = 0; c < SW_TUNE_CANDIDATES; ++c) {
+    local.cand_rows[c] = kTuneR[c];
+    local.cand_waves[c] = kTuneW[c];
+  }
+  for (int c = 0; c < SW_TUNE_INTRA_CANDIDATES; ++c) {
+    local.intra_cand_rows[c] = kTuneIR[c];
+    local.intra_cand_waves[c] = kTuneIW[c];
+  }
+  // representative lengths: the defaults, or the median of the caller's
+  // lengths in each bucket (0: none there, the bucket stays untuned)
+  int rep_len[SW_TUNE_BUCKETS] = {192, 448, 1280, 4096};
+  if (n_lens > 0) {
+    std::vector<int32_t> by[SW_TUNE_BUCKETS];
+    for (int32_t i = 0; i < n_lens; ++i) {
+      if (query_lens[i] < 0 || query_lens[i] > SW_MAX_LEN)
+        return fail(SW_EINVAL, "query length out of range at " + std::to_string(i));
+      if (query_lens[i] > 0) by[tune_bucket(query_lens[i])].push_back(query_lens[i]);
+    }
+    for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
+      std::sort(by[b].begin(), by[b].end());
+      rep_len[b] = by[b].empty() ? 0 : by[b][by[b].size() / 2];
+    }
+  }
+  for (int b = 0; b < SW_TUNE_BUCKETS; ++b) local.query_len[b] = rep_len[b];
+  auto apply = [&]() {
+    for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
+      db->tune_rows[b] = local.rows[b];
+      db->tune_waves[b] = local.waves[b];
+      db->tune_brows[b] = local.batch_rows[b];
+      db->tune_bwaves[b] = local.batch_waves[b];
+      db->tune_irows[b] = local.intra_rows[b];
+      db->tune_iwaves[b] = local.intra_waves[b];
+    }
+  };
+  const std::string key = cache_path ? tune_key(db, rep_len) : std::string();
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "r");
+    if (f) {
+      char line[1024];
+      bool found = false;
+      while (!found && fgets(line, sizeof(line), f)) {
+        char* tab = strchr(line, '\t');
+        if (!tab || std::string(line, tab) != key) continue;
+        int v[6 * SW_TUNE_BUCKETS];
+        int n = 0, off = 0, used = 0;
+        const char* p = tab + 1;
+        while (n < 6 * SW_TUNE_BUCKETS && sscanf(p + off, "%d%n", &v[n], &used) == 1) {
+          off += used;
+          ++n;
+        }
+        if (n != 6 * SW_TUNE_BUCKETS) continue;
+        for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
+          local.rows[b] = v[6 * b];
+          local.waves[b] = v[6 * b + 1];
+          local.batch_rows[b] = v[6 * b + 2];
+          local.batch_waves[b] = v[6 * b + 3];
+          local.intra_rows[b] = v[6 * b + 4];
+          local.intra_waves[b] = v[6 * b + 5];
+        }
+        found = true;
+      }
+      fclose(f);
+      if (found) {
+        local.from_cache = 1;
+        apply();
+        if (rep) *rep = local;
+        set_error("");
+        return SW_OK;
+      }
+    }
+  }
+  if (db->d->n_seqs == 0 || db->d->plan.n_bins == 0) {
+    if (rep) *rep = local;
+    set_error("");
+    return SW_OK;
+  }
   Matrix mat{};
   // a BLOSUM-like synthetic matrix is enough to time the kernels: the cost
   // does not depend on the scores; +5 on the diagonal, -1 elsewhere
   for (int a = 0; a < SW_ALPHA; ++a)
     for (int b = 0; b < SW_ALPHA; ++b) mat.v[a * SW_ALPHA + b] = (int8_t)(a == b ? 5 : -1);
-  const int max_m = rep_len[SW_TUNE_BUCKETS - 1];
+  int max_m = 1;
+  for (int b = 0; b < SW_TUNE_BUCKETS; ++b) max_m = std::max(max_m, rep_len[b]);
+  hipError_t e;
+  hipStream_t s = db->own_stream;
   DevBuf<uint8_t> dq;
   DevBuf<int32_t> dout;
   dq.users = &db->users;
@@ -1916,87 +2055,93 @@ static int impl_autotune(swdb::Searcher* db, sw_tune_report* rep) {
     return hip_fail(e, "autotune upload");
   const bool saved_timing = db->timing, saved_graphs = db->use_graphs;
   const int32_t saved_r = db->opt_rows, saved_w = db->opt_waves;
+  const int32_t saved_ir = db->opt_intra_rows, saved_iw = db->opt_intra_waves;
   db->timing = true;
   db->use_graphs = false;
-  sw_tune_report local{};
   int rc = SW_OK;
   // untuned while measuring, so the fitted candidate (0, 0) is what it says
   for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
-    db->tune_rows[b] = db->tune_waves[b] = db->tune_brows[b] = db->tune_bwaves[b] = 0;
-  int pick[SW_TUNE_BUCKETS] = {}, bpick[SW_TUNE_BUCKETS] = {};
+    db->tune_rows[b] = db->tune_waves[b] = db->tune_brows[b] = db->tune_bwaves[b] =
+        db->tune_irows[b] = db->tune_iwaves[b] = 0;
+  const bool has_long = db->d->plan.n_long > 0;
   for (int b = 0; b < SW_TUNE_BUCKETS && rc == SW_OK; ++b) {
     const int m = rep_len[b];
-    local.query_len[b] = m;
-    double best = -1, bbest = -1;
+    if (m <= 0) continue;
+    double best = -1, bbest = -1, ibest = 1e300;
+    int pick = 0, bpick = 0, ipick = -1;
+    db->opt_intra_rows = db->opt_intra_waves = 0;
     for (int c = 0; c < SW_TUNE_CANDIDATES && rc == SW_OK; ++c) {
-      db->opt_rows = cand_r[c];
-      db->opt_waves = cand_w[c];
+      db->opt_rows = kTuneR[c];
+      db->opt_waves = kTuneW[c];
       // single query: warm up, then two timed launches
       for (int rpt = 0; rpt < 3 && rc == SW_OK; ++rpt) {
-        if (rpt == 1) { db->timed.clear(); db->stats = sw_stats{}; }
+        if (rpt == 1) { (void)drain_timed(db, kTimeInter); db->stats = sw_stats{}; }
         rc = enqueue_search(db, dq.p, m, mat, 10, 2, dout.p, s);
       }
       if (rc != SW_OK) break;
-      float ms_inter = 0;
-      for (auto& t : db->timed) {
-        (void)hipEventSynchronize(t.b);
-        float ms = 0;
-        if (t.kind == kTimeInter && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) ms_inter += ms;
-        db->ev_pool.push_back(t.a);
-        db->ev_pool.push_back(t.b);
-      }
-      db->timed.clear();
-      const double gc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
+      float ms = drain_timed(db, kTimeInter);
+      const double gc = ms > 0 ? (double)db->stats.inter_cells / (ms * 1e6) : 0;
       local.gcups[b][c] = (float)gc;
-      if (gc > best) { best = gc; pick[b] = c; }
+      if (gc > best) { best = gc; pick = c; }
       // batched: one pair of queries of this length
       const int64_t qo[3] = {0, m, 2 * (int64_t)m};
       db->stats = sw_stats{};
       for (int rpt = 0; rpt < 2 && rc == SW_OK; ++rpt) {
-        if (rpt == 1) { db->timed.clear(); db->stats = sw_stats{}; }
+        if (rpt == 1) { (void)drain_timed(db, kTimeInter); db->stats = sw_stats{}; }
         rc = run_batch(db, dq.p, qo, 2, mat, 10, 2, dout.p, s);
       }
       if (rc != SW_OK) break;
-      ms_inter = 0;
-      for (auto& t : db->timed) {
-        (void)hipEventSynchronize(t.b);
-        float ms = 0;
-        if (t.kind == kTimeInter && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) ms_inter += ms;
-        db->ev_pool.push_back(t.a);
-        db->ev_pool.push_back(t.b);
-      }
-      db->timed.clear();
-      const double bgc = ms_inter > 0 ? (double)db->stats.inter_cells / (ms_inter * 1e6) : 0;
+      ms = drain_timed(db, kTimeInter);
+      const double bgc = ms > 0 ? (double)db->stats.inter_cells / (ms * 1e6) : 0;
       local.batch_gcups[b][c] = (float)bgc;
-      if (bgc > bbest) { bbest = bgc; bpick[b] = c; }
+      if (bgc > bbest) { bbest = bgc; bpick = c; }
     }
-    local.rows[b] = cand_r[pick[b]];
-    local.waves[b] = cand_w[pick[b]];
-    local.batch_rows[b] = cand_r[bpick[b]];
-    local.batch_waves[b] = cand_w[bpick[b]];
-  }
-  for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
-    db->tune_rows[b] = local.rows[b];
-    db->tune_waves[b] = local.waves[b];
-    db->tune_brows[b] = local.batch_rows[b];
-    db->tune_bwaves[b] = local.batch_waves[b];
+    // the long-pair kernel of single searches, beside the chosen inter-task
+    // schedule
+    db->opt_rows = kTuneR[pick];
+    db->opt_waves = kTuneW[pick];
+    for (int c = 0; has_long && c < SW_TUNE_INTRA_CANDIDATES && rc == SW_OK; ++c) {
+      db->opt_intra_rows = kTuneIR[c];
+      db->opt_intra_waves = kTuneIW[c];
+      for (int rpt = 0; rpt < 2 && rc == SW_OK; ++rpt) {
+        if (rpt == 1) (void)drain_timed(db, kTimeIntra);
+        rc = enqueue_search(db, dq.p, m, mat, 10, 2, dout.p, s);
+      }
+      if (rc != SW_OK) break;
+      const float ms = drain_timed(db, kTimeIntra);
+      local.intra_ms[b][c] = ms;
+      if (ms > 0 && ms < ibest) { ibest = ms; ipick = c; }
+    }
+    local.rows[b] = kTuneR[pick];
+    local.waves[b] = kTuneW[pick];
+    local.batch_rows[b] = kTuneR[bpick];
+    local.batch_waves[b] = kTuneW[bpick];
+    local.intra_rows[b] = ipick >= 0 ? kTuneIR[ipick] : 0;
+    local.intra_waves[b] = ipick >= 0 ? kTuneIW[ipick] : 0;
   }
   (void)hipStreamSynchronize(s);
+  (void)drain_timed(db, -1);
   db->batch.release();
   db->timing = saved_timing;
   db->use_graphs = saved_graphs;
   db->opt_rows = saved_r;
   db->opt_waves = saved_w;
+  db->opt_intra_rows = saved_ir;
+  db->opt_intra_waves = saved_iw;
   db->stats = sw_stats{};
-  for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
-    for (int c = 0; c < SW_TUNE_CANDIDATES; ++c) {
-      local.cand_rows[c] = cand_r[c];
-      local.cand_waves[c] = cand_w[c];
-    }
-  if (rc != SW_OK) {
+  if (rc != SW_OK) return rc;
+  // (0, 0) chosen means "fitted": stored as untuned so the fit stays per query
+  apply();
+  if (cache_path) {
+    FILE* f = fopen(cache_path, "a");
+    if (!f) return fail(SW_EINVAL, std::string("cannot write the tuning cache ") + cache_path);
+    fprintf(f, "%s\t", key.c_str());
     for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
-      db->tune_rows[b] = db->tune_waves[b] = db->tune_brows[b] = db->tune_bwaves[b] = 0;
-    return rc;
+      fprintf(f, "%d %d %d %d %d %d ", local.rows[b], local.waves[b], local.batch_rows[b],
+              local.batch_waves[b], local.intra_rows[b], local.intra_waves[b]);
+    fprintf(f, "\n");
+    if (fclose(f) != 0)
+      return fail(SW_EINVAL, std::string("cannot write the tuning cache ") + cache_path);
   }
   if (rep) *rep = local;
   set_error("");
@@ -2117,7 +2262,13 @@ int sw_set_option(sw_db* h, int32_t key, int64_t value) {
   return impl_set_option(S_of(h), key, value);
 }
 int sw_get_stats(sw_db* h, sw_stats* out) { return impl_get_stats(S_of(h), out); }
-int sw_autotune(sw_db* h, sw_tune_report* report) { return impl_autotune(S_of(h), report); }
+int sw_autotune(sw_db* h, sw_tune_report* report) {
+  return impl_autotune(S_of(h), nullptr, 0, nullptr, report);
+}
+int sw_autotune_ex(sw_db* h, const int32_t* query_lens, int32_t n_lens, const char* cache_path,
+                   sw_tune_report* report) {
+  return impl_autotune(S_of(h), query_lens, n_lens, cache_path, report);
+}
 
 int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
   using namespace swdb;
@@ -2150,6 +2301,8 @@ int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
       c->s.tune_waves[b] = h->main.tune_waves[b];
       c->s.tune_brows[b] = h->main.tune_brows[b];
       c->s.tune_bwaves[b] = h->main.tune_bwaves[b];
+      c->s.tune_irows[b] = h->main.tune_irows[b];
+      c->s.tune_iwaves[b] = h->main.tune_iwaves[b];
     }
   }
   *out_ctx = c;

@@ -592,24 +592,47 @@ def test_full_size_batched_workload_full_rows(sw):
         _check_bounds(got[qi], q, lens)
 
 
-def test_autotune_then_searches_stay_exact(sw):
+_TUNE_FORMS = [(0, 0), (20, 12), (18, 12), (16, 12), (14, 12), (12, 12), (14, 16), (12, 16)]
+_TUNE_INTRA = [(2, 1), (4, 1), (8, 1), (2, 2), (4, 2), (8, 2), (2, 4), (4, 4), (8, 4), (2, 8),
+               (4, 8)]
+
+
+def test_autotune_then_searches_stay_exact(sw, tmp_path):
+    """The autotuner measures every inter-task form and every long-pair
+    schedule, for the caller's query lengths; a second handle of the same
+    database applies the cached choice without measuring; searches stay exact
+    with the tuned schedules (single, batched, and in a context)."""
     res, offs = _ragged_db(30)
     qs = _queries(31, [150, 700, 1300, 2500])
+    lens = [len(q) for q in qs]
+    cache = str(tmp_path / "tune.txt")
     say("autotune")
     with sw.Database(res, offs) as db:
         rep = db.autotune()
-        assert len(rep["buckets"]) == 4
+        assert [b["query_len"] for b in rep["buckets"]] == [192, 448, 1280, 4096]
         for b in rep["buckets"]:
-            assert b["chosen"] in [(16, 8), (0, 0), (32, 4), (32, 8)]
-            assert b["batch_chosen"] in [(16, 8), (0, 0), (32, 4), (32, 8)]
-            assert max(b["gcups"].values()) > 0 and max(b["batch_gcups"].values()) > 0
+            assert b["chosen"] in _TUNE_FORMS and b["batch_chosen"] in _TUNE_FORMS
+            assert b["intra_chosen"] in _TUNE_INTRA          # the database has a long sequence
+            assert min(b["gcups"].values()) > 0 and min(b["batch_gcups"].values()) > 0
+            assert min(b["intra_ms"].values()) > 0
+        rep = db.autotune(lens, cache=cache)
+        assert not rep["from_cache"]
+        assert [b["query_len"] for b in rep["buckets"]] == [150, 700, 1300, 2500]
+        chosen = [(b["chosen"], b["batch_chosen"], b["intra_chosen"]) for b in rep["buckets"]]
         single = [db.search(q, B62, 10, 2) for q in qs]
         batch = db.search_batch(qs, B62, 10, 2)
         ctx = db.context()           # contexts inherit the tuned table
         ctx.close()
-    for q, a, b in zip(qs, single, batch):
+    assert len(open(cache).read().splitlines()) == 1
+    with sw.Database(res, offs) as db:
+        rep = db.autotune(lens, cache=cache)
+        assert rep["from_cache"]
+        assert [(b["chosen"], b["batch_chosen"], b["intra_chosen"])
+                for b in rep["buckets"]] == chosen
+        again = [db.search(q, B62, 10, 2) for q in qs]
+    for q, a, b, c in zip(qs, single, batch, again):
         want = _oracle(q, res, offs)
-        assert (a == want).all() and (b == want).all()
+        assert (a == want).all() and (b == want).all() and (c == want).all()
 
 
 def test_full_size_long_mix_workload_sampled(sw):
