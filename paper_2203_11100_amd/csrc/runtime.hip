@@ -38,7 +38,11 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+// HIP keeps the last failing call's error until hipGetLastError reads it,
+// and the launch checks read it: an error already handled here is consumed
+// so that it cannot surface at the next launch.
 int hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();
   return fail(SW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
@@ -81,7 +85,12 @@ struct DevBuf {
     }
     if (n == 0) n = 1;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), n * sizeof(T));
-    if (e == hipSuccess) cap = n;
+    if (e == hipSuccess) {
+      cap = n;
+    } else {
+      p = nullptr;
+      (void)hipGetLastError();   // handled by the caller: not a later launch's error
+    }
     return e;
   }
   void release() {
@@ -466,7 +475,10 @@ hipEvent_t pool_event(Searcher* db) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();   // timing is skipped; not a later launch's error
+    return nullptr;
+  }
   return e;
 }
 
