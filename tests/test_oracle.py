@@ -417,3 +417,50 @@ def test_search_mode_matches_per_sequence():
         got = ocpu.search_mode(q, res, offs, B62, 10, 2, mode, threads=4)
         for i in range(0, 300, 11):
             assert got[i] == ocpu.score_mode(q, res[offs[i]:offs[i + 1]], B62, 10, 2, mode)
+
+
+# ------------------------------------------------------------------------ DNA
+# DNA searches use codes 0..4 (A C G T N) and a match/mismatch table; the
+# oracle's arithmetic is the same, so these pin the table and the closed
+# forms that hold for nucleotide scoring.
+def test_dna_table_and_encoding():
+    D = swinputs.dna_matrix(5, 4, -2)
+    assert D.shape == (24, 24) and (D == D.T).all()
+    assert all(D[i, i] == 5 for i in range(4))
+    assert all(D[i, j] == -4 for i in range(4) for j in range(4) if i != j)
+    assert (D[4, :] == -2).all() and (D[:, 4] == -2).all()
+    assert list(swinputs.encode_dna("ACGTNacgtuX")) == [0, 1, 2, 3, 4, 0, 1, 2, 3, 3, 4]
+    assert swinputs.decode_dna(swinputs.encode_dna("GATTACA")) == "GATTACA"
+
+
+def test_dna_self_and_embedded_copy_closed_form():
+    """Match +5 beats every mismatch and gap, so a base sequence against
+    itself, or against any sequence that contains it, scores 5 per base."""
+    rng = np.random.default_rng(21)
+    D = swinputs.dna_matrix(5, 4, -2)
+    for m in (1, 7, 60, 333):
+        q = swinputs.random_dna(m, rng)
+        assert ocpu.score(q, q, D, 10, 2) == 5 * m
+        t = np.concatenate([swinputs.random_dna(int(rng.integers(0, 90)), rng), q,
+                            swinputs.random_dna(int(rng.integers(0, 90)), rng)])
+        assert ocpu.score(q, t, D, 16, 4) == 5 * m
+        assert oracle.sw_gotoh(q[:40], t, D, 16, 4) == 5 * min(m, 40)
+
+
+def test_dna_unit_match_prohibitive_rest_is_longest_common_substring():
+    """Match 1, mismatch and N -100, gaps beyond any gain: the score is the
+    length of the longest common substring (checked by direct search)."""
+    rng = np.random.default_rng(22)
+    D = swinputs.dna_matrix(1, 100, -100)
+    for _ in range(40):
+        a = swinputs.random_dna(int(rng.integers(0, 25)), rng)
+        b = swinputs.random_dna(int(rng.integers(0, 25)), rng)
+        best = 0
+        for i in range(len(a)):
+            for j in range(len(b)):
+                k = 0
+                while i + k < len(a) and j + k < len(b) and a[i + k] == b[j + k]:
+                    k += 1
+                best = max(best, k)
+        assert ocpu.score(a, b, D, 100, 100) == best
+        assert oracle.sw_bruteforce(a[:6], b[:6], D, 100, 100) == ocpu.score(a[:6], b[:6], D, 100, 100)
