@@ -38,6 +38,9 @@
  *  - The substitution matrix is int8_t[SW_ALPHA * SW_ALPHA], row-major,
  *    matrix[q * SW_ALPHA + t] = score of query residue q against database
  *    residue t.  It is a host pointer, read during the call only.
+ *  - Nothing depends on the alphabet beyond the codes and the matrix: DNA
+ *    (SW# aligns DNA as well as protein, paper section 2.3) uses codes 0..4
+ *    for A C G T N and a match/mismatch table in the same calls.
  *  - Gap penalties: 0 <= gap_extend <= gap_open <= SW_MAX_GAP.  (With
  *    gap_open < gap_extend the recurrence and the definition above differ;
  *    such calls are rejected.)

@@ -558,9 +558,10 @@ def test_full_size_batched_workload_full_rows(sw):
     """The full batched workload (the 20 plain queries + 200 of 50..5,000
     residues, 220 queries x 200,000 sequences) as the benchmark runs it: one
     batched search planned and captured into a HIP graph, then replayed.
-    Whole rows compared with the oracle: the shortest and the longest query,
-    and both halves of the two pairs of shortest queries (queries are paired
-    two per lane in length order); every other row checked by bounds."""
+    Every score equals the single-query search of the same query; whole rows
+    compared with the oracle: the shortest and the longest query, and both
+    halves of the two pairs of shortest queries (queries are paired two per
+    lane in length order); every row checked by bounds."""
     import torch
     from conftest import workload, oracle_row
     w = workload("batched")
@@ -578,6 +579,16 @@ def test_full_size_batched_workload_full_rows(sw):
         db.search_batch_async(cat, qoffs, w.matrix, 10, 2, out)     # graph replay
         torch.cuda.synchronize()
         got = out.cpu().numpy()
+        # every row against the single-query search of the same query (a
+        # different kernel, itself compared with the oracle row by row above)
+        single = torch.empty(db.n_seqs, dtype=torch.int32, device="cuda")
+        for qi, q in enumerate(w.queries):
+            db.search_async(cat[qoffs[qi]:qoffs[qi + 1]], w.matrix, 10, 2, single)
+            row = single.cpu().numpy()
+            bad = np.nonzero(got[qi] != row)[0]
+            assert len(bad) == 0, (qi, qlens[qi], bad[:5], got[qi][bad[:5]], row[bad[:5]])
+        say("batched: all %d x %d scores equal the single-query searches"
+            % (len(w.queries), w.n_seqs))
         del out
     # the library pairs queries in stable length order, longest first
     order = sorted(range(len(qlens)), key=lambda q: -qlens[q])
