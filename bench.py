@@ -289,7 +289,7 @@ def hybrid_leg(db, w, host_rt, steps=2):
     """The plain step through sw_search_hybrid (host cores take bins from the
     back of the work order while the GPU takes chunks from the front),
     against the same step through the GPU-only host-buffer call."""
-    totals = {"gpu_cells": 0, "cpu_cells": 0, "cpu_bins": 0, "gpu_bins": 0}
+    totals = {"gpu_cells": 0, "cpu_cells": 0, "cpu_seqs": 0, "gpu_bins": 0}
     threads = 0
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -304,7 +304,7 @@ def hybrid_leg(db, w, host_rt, steps=2):
          "step_time_change": dt * 1e3 / host_rt["ms_per_step"] - 1.0,
          "cpu_threads": threads,
          "cpu_cell_share": totals["cpu_cells"] / max(1, totals["cpu_cells"] + totals["gpu_cells"]),
-         "cpu_bins_per_step": totals["cpu_bins"] / steps,
+         "cpu_seqs_per_step": totals["cpu_seqs"] / steps,
          "gpu_bins_per_step": totals["gpu_bins"] / steps,
          "form": "sw_search_hybrid per query (host buffers), vs sw_search per query"}
     log("hybrid: %s" % r)

@@ -212,7 +212,8 @@ int sw_search_topk_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
  * and the GPU's rescoring stay on the GPU.  Scores are identical to
  * sw_search.  Host buffers, synchronous; `stats` may be NULL. */
 typedef struct sw_hybrid_stats {
-  int64_t gpu_bins, cpu_bins;      /* short bins scored by each side */
+  int64_t gpu_bins;                /* short bins the GPU scored */
+  int64_t cpu_seqs;                /* short sequences the host threads scored */
   int64_t gpu_cells, cpu_cells;    /* cells (query length x residues) of each side */
   int32_t cpu_threads;             /* host threads used */
   float ms;                        /* wall time of the call */
@@ -284,6 +285,10 @@ enum sw_option {
                              16) */
   SW_OPT_INTRA_ROWS = 5,  /* intra-task query rows per lane: 0 (auto), 2, 4, 8 */
   SW_OPT_INTRA_WAVES = 6, /* intra-task waves per long sequence: 0 (auto), 1, 2, 4, 8 */
+  SW_OPT_HYBRID_SHARE = 8, /* hybrid search: 0 (default) plans the host's share
+                             from measured rates; 1..1000 fixes it at that many
+                             thousandths of the short bins' cells, with no
+                             give-back (for tests and experiments) */
   SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph
                              (default 1; graphs are not used while TIMING is on) */
 };

@@ -22,6 +22,7 @@ SW_DEFAULT_LONG_THRESHOLD = 2048
 SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 1, 2, 3, 4, 5
 SW_OPT_INTRA_WAVES = 6
 SW_OPT_GRAPHS = 7
+SW_OPT_HYBRID_SHARE = 8
 SW_MAX_TOPK = 4096
 SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1, 2
 
@@ -53,7 +54,7 @@ class Stats(ctypes.Structure):
 
 
 class HybridStats(ctypes.Structure):
-    _fields_ = [("gpu_bins", ctypes.c_int64), ("cpu_bins", ctypes.c_int64),
+    _fields_ = [("gpu_bins", ctypes.c_int64), ("cpu_seqs", ctypes.c_int64),
                 ("gpu_cells", ctypes.c_int64), ("cpu_cells", ctypes.c_int64),
                 ("cpu_threads", ctypes.c_int32), ("ms", ctypes.c_float)]
 

@@ -214,6 +214,11 @@ struct Searcher {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_in = nullptr, ev_out = nullptr;
   hipEvent_t ev_caller = nullptr;   // end of the last work enqueued on a caller's stream
   hipEvent_t ev_chunk[2] = {nullptr, nullptr};   // hybrid search: GPU chunks in flight
+  // hybrid search: running averages of the GPU's short-bin rate and one host
+  // thread's rate, cells per second (seeded low for the host, so that a
+  // first call gives it little)
+  double hyb_gpu_rate = 3e12, hyb_cpu_rate = 2e8;
+  int32_t hyb_share = 0;            // SW_OPT_HYBRID_SHARE: fixed host share, thousandths
   // timing: (kind, start, end) event pairs recorded since the last
   // sw_get_stats; events are recycled through `ev_pool`
   struct Timed { int kind; hipEvent_t a, b; };
@@ -1512,26 +1517,25 @@ static int impl_search_topk(swdb::Searcher* db, const uint8_t* query, int32_t qu
 }
 
 // ------------------------------------------------------------ hybrid search
-constexpr int64_t kHybridMinChunk = 32;   // bins per GPU launch, at least
+constexpr int64_t kHybridMinChunk = 32;   // bins per later GPU launch, at least
 
-static void hybrid_score_bin(const swdb::DbData& D, const swdb::cpu::Profile& prof, int64_t b,
-                             int32_t go, int32_t ge, int32_t* out, swdb::cpu::Workspace* w,
-                             int64_t* cells) {
-  const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
-  for (int k = 0; k < SW_BIN_SEQS; ++k) {
-    const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
-    if (sid < 0) continue;
-    const int64_t at = D.h_offs[(size_t)sid];
-    const int n = (int)(D.h_offs[(size_t)sid + 1] - at);
-    out[sid] = swdb::cpu::score(prof, D.h_res.data() + at, n, go, ge, w);
-    *cells += (int64_t)n * prof.m;
-  }
-}
-
+// The hybrid search's shared work order is the short bins' slots in
+// length-sorted order (slot k of bin b is position 128 b + k).  The GPU
+// takes whole bins from the front in chunks; the host threads take single
+// sequences from the back (the shortest first).  The two may overlap in the
+// bin where they meet (a sequence scored by both sides gets the same exact
+// score).  The split is planned from measured rates: the GPU's first chunk
+// leaves the host about twice the share its speed suggests, and a host
+// thread only keeps a sequence it expects to finish before the planned end;
+// a sequence given back (and every longer one) goes to the GPU.  When the
+// GPU has no bin left it stops the host threads, waits for their current
+// sequences and launches one last chunk for any bin a given-back sequence
+// lies in, so every slot is scored by at least one side.
 static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t query_len,
                               const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
                               int32_t cpu_threads, int32_t* out_scores, sw_hybrid_stats* hst) {
   using namespace swdb;
+  using clock = std::chrono::steady_clock;
   int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, out_scores);
   if (rc != SW_OK) return rc;
   if (cpu_threads < 0 || cpu_threads > 1024) return fail(SW_EINVAL, "cpu_threads must be 0..1024");
@@ -1543,7 +1547,7 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   const DbData& D = *db->d;
   const int64_t n = D.n_seqs, n_bins = D.plan.n_bins;
   sw_hybrid_stats st{};
-  const auto t0 = std::chrono::steady_clock::now();
+  const auto t0 = clock::now();
   const int threads = cpu_threads > 0 ? cpu_threads
                                       : std::max(1, (int)std::thread::hardware_concurrency() - 1);
   st.cpu_threads = threads;
@@ -1558,12 +1562,25 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
       (e = db->out_stage.reserve((size_t)n)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
   std::vector<int32_t> gpu_scores;
+  std::vector<int64_t> cum;   // cells of the bins before bin b, b = 0 .. n_bins
+  std::vector<uint8_t> host_done;   // per slot: scored by a host thread
   cpu::Profile prof;
   try {
     gpu_scores.resize((size_t)n);
+    cum.assign((size_t)n_bins + 1, 0);
+    host_done.assign((size_t)n_bins * SW_BIN_SEQS, 0);
     cpu::build_profile(query, query_len, matrix, &prof);
   } catch (...) {
     return fail(SW_ENOMEM, "host allocation failed");
+  }
+  for (int64_t b = 0; b < n_bins; ++b) {
+    const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
+    int64_t res = 0;
+    for (int k = 0; k < SW_BIN_SEQS; ++k) {
+      const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
+      if (sid >= 0) res += D.h_offs[(size_t)sid + 1] - D.h_offs[(size_t)sid];
+    }
+    cum[(size_t)b + 1] = cum[(size_t)b] + res * query_len;
   }
   hipStream_t s = db->own_stream;
   if ((e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
@@ -1573,47 +1590,102 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   SearchScratch X;
   if ((rc = reserve_search_scratch(db, sh, &X)) != SW_OK) return rc;
 
-  // the shared work order: the GPU takes chunks of bins from the front
-  // (longest first), the host threads single bins from the back
-  std::mutex mu;
-  int64_t front = 0, back = n_bins;
-  std::atomic<int64_t> cpu_cells{0}, cpu_bins{0};
+  // the plan: expected time of the short bins with both sides working, the
+  // host's expected share, and the deadline by which a host thread must be
+  // done with anything it takes
+  const double cells_all = (double)cum[(size_t)n_bins];
+  const double r_gpu = db->hyb_gpu_rate, r_cpu = db->hyb_cpu_rate;
+  const double t_plan = cells_all / (r_gpu + threads * r_cpu);
+  const double host_share = db->hyb_share > 0 ? cells_all * db->hyb_share / 2000.0
+                                              : threads * r_cpu * t_plan;
+  // a fixed share (SW_OPT_HYBRID_SHARE) has no deadline: the host keeps
+  // what it takes
+  const auto deadline = db->hyb_share > 0 ? clock::time_point::max()
+                                          : t0 + std::chrono::duration_cast<clock::duration>(
+                                                     std::chrono::duration<double>(t_plan));
+  const int64_t first_cells = (int64_t)std::max(0.0, cells_all - 2.0 * host_share);
+  std::atomic<int64_t> back{n_bins * SW_BIN_SEQS};   // host: the next slot is back - 1
+  std::atomic<int64_t> front{0};                      // GPU: the next bin
+  std::atomic<int64_t> given_back{0};                 // 1 + the highest slot given back
+  std::atomic<bool> gpu_done{false};
+  std::atomic<int64_t> cpu_cells{0}, cpu_seqs{0};
+  std::atomic<int64_t> cpu_ns{0};
   std::vector<std::thread> pool;
   auto worker = [&]() {
     cpu::Workspace w;
-    int64_t cells = 0, bins = 0;
-    for (;;) {
-      int64_t b;
-      {
-        std::lock_guard<std::mutex> l(mu);
-        if (back <= front) break;
-        b = --back;
+    int64_t cells = 0, seqs = 0, ns = 0;
+    while (!gpu_done.load(std::memory_order_relaxed)) {
+      const int64_t slot = back.fetch_sub(1) - 1;
+      // the bins the GPU has taken stay with it
+      if (slot < front.load() * SW_BIN_SEQS) break;
+      const int64_t b = slot / SW_BIN_SEQS;
+      const int32_t sid = D.h_slots[(size_t)(D.h_bins[(size_t)b * 4 + 3] + slot % SW_BIN_SEQS)];
+      if (sid < 0) continue;
+      const int64_t at = D.h_offs[(size_t)sid];
+      const int len = (int)(D.h_offs[(size_t)sid + 1] - at);
+      const int64_t c = (int64_t)len * query_len;
+      const auto now = clock::now();
+      if (deadline != clock::time_point::max() &&
+          now + std::chrono::duration_cast<clock::duration>(std::chrono::duration<double>(c / r_cpu)) >
+              deadline) {
+        // not this one: leave it (and the longer rest) to the GPU
+        int64_t top = given_back.load();
+        while (top < slot + 1 && !given_back.compare_exchange_weak(top, slot + 1)) {
+        }
+        gpu_done = true;          // stops the other host threads too
+        break;
       }
-      hybrid_score_bin(D, prof, b, gap_open, gap_extend, out_scores, &w, &cells);
-      ++bins;
+      out_scores[sid] = cpu::score(prof, D.h_res.data() + at, len, gap_open, gap_extend, &w);
+      host_done[(size_t)slot] = 1;
+      ns += std::chrono::duration_cast<std::chrono::nanoseconds>(clock::now() - now).count();
+      cells += c;
+      ++seqs;
     }
     cpu_cells += cells;
-    cpu_bins += bins;
+    cpu_seqs += seqs;
+    cpu_ns += ns;
   };
   try {
     for (int t = 0; t < threads; ++t) pool.emplace_back(worker);
   } catch (...) {
-    std::lock_guard<std::mutex> l(mu);
-    back = front;   // no more host work
+    gpu_done = true;   // no more host work
   }
   int64_t gpu_bins = 0;
+  auto t_gpu0 = clock::now(), t_gpu1 = t_gpu0;
+  // first bin the GPU does not need to take: every slot from there on is
+  // held by a host thread (bins a host thread has started or given a slot
+  // back in are taken too)
+  auto gpu_end = [&]() {
+    const int64_t to = std::max<int64_t>({back.load(), given_back.load(), 0});
+    return (to + SW_BIN_SEQS - 1) / SW_BIN_SEQS;
+  };
+  bool joined = false;
   BinRunner runner = [&](InterArgs& a, int R, int W, hipStream_t st_) -> int {
     int k = 0;
+    t_gpu0 = clock::now();
     for (;;) {
-      int64_t b0, take;
-      {
-        std::lock_guard<std::mutex> l(mu);
-        const int64_t rem = back - front;
-        if (rem <= 0) break;
-        take = std::min(rem, std::max(kHybridMinChunk, rem / 4));
-        b0 = front;
-        front += take;
+      const int64_t b0 = front.load();
+      int64_t end = gpu_end();
+      if (end <= b0 && !joined) {
+        // nothing left for the GPU: stop the host threads, wait for their
+        // current sequences, and look again
+        gpu_done = true;
+        for (auto& t : pool) t.join();
+        joined = true;
+        end = gpu_end();
       }
+      const int64_t rem = end - b0;
+      if (rem <= 0) break;
+      int64_t take;
+      if (k == 0) {   // most of the work at once, leaving the host's planned share
+        take = std::upper_bound(cum.begin() + b0, cum.begin() + end + 1, first_cells) -
+               (cum.begin() + b0) - 1;
+        take = std::max<int64_t>(take, std::min(rem, kHybridMinChunk));
+      } else {
+        take = std::min(rem, std::max(kHybridMinChunk, rem / 4));
+      }
+      take = std::min(take, rem);
+      front.store(b0 + take);
       a.bin_begin = (int32_t)b0;
       hipError_t err;
       if ((err = launch_inter(R, W, (int)take, a, st_)) != hipSuccess)
@@ -1627,38 +1699,48 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
       gpu_bins += take;
       ++k;
     }
+    if (k > 0 && hipEventSynchronize(db->ev_chunk[(k - 1) & 1]) != hipSuccess)
+      (void)hipGetLastError();   // reported by the stream synchronisation below
+    t_gpu1 = clock::now();
+    gpu_done = true;
     return SW_OK;
   };
   Matrix mat;
   memcpy(mat.v, matrix, sizeof(mat.v));
   rc = enqueue_search_kernels(db, sh, X, db->q_stage.p, query_len, mat, gap_open, gap_extend,
                               db->out_stage.p, s, &runner);
-  if (rc != SW_OK) {
-    std::lock_guard<std::mutex> l(mu);
-    back = front;
-  }
-  for (auto& t : pool) t.join();
+  gpu_done = true;
+  if (!joined)
+    for (auto& t : pool) t.join();
   if (rc == SW_OK &&
       (e = hipMemcpyAsync(gpu_scores.data(), db->out_stage.p, (size_t)n * 4, hipMemcpyDeviceToHost,
                           s)) != hipSuccess)
     rc = hip_fail(e, "score download");
   if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == SW_OK) rc = hip_fail(e, "search");
   if (rc != SW_OK) return rc;
-  // GPU share: bins before the split point and the long list
-  const int64_t split = front;
-  for (int64_t b = 0; b < split; ++b) {
+  // GPU share: the bins it took (except the slots a host thread scored,
+  // which hold the same scores already) and the long list; every slot
+  // outside the GPU's bins was scored by a host thread
+  for (int64_t b = 0; b < front.load(); ++b) {
     const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
     for (int k = 0; k < SW_BIN_SEQS; ++k) {
+      if (host_done[(size_t)(b * SW_BIN_SEQS + k)]) continue;
       const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
       if (sid >= 0) out_scores[sid] = gpu_scores[(size_t)sid];
     }
   }
   for (int32_t sid : D.long_ids) out_scores[sid] = gpu_scores[(size_t)sid];
+  // running averages of both sides' rates for the next plan
+  const double gpu_s = std::chrono::duration<double>(t_gpu1 - t_gpu0).count();
+  const double gpu_short = cells_all - (double)cpu_cells.load();
+  if (gpu_s > 0 && gpu_short > 0) db->hyb_gpu_rate = 0.5 * db->hyb_gpu_rate + 0.5 * gpu_short / gpu_s;
+  if (cpu_ns.load() > 0 && cpu_cells.load() > 0)
+    db->hyb_cpu_rate = 0.5 * db->hyb_cpu_rate + 0.5 * (double)cpu_cells.load() / (cpu_ns.load() * 1e-9);
   st.gpu_bins = gpu_bins;
-  st.cpu_bins = cpu_bins.load();
+  st.cpu_seqs = cpu_seqs.load();
   st.cpu_cells = cpu_cells.load();
   st.gpu_cells = (int64_t)query_len * D.n_res - st.cpu_cells;
-  st.ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  st.ms = std::chrono::duration<float, std::milli>(clock::now() - t0).count();
   if (hst) *hst = st;
   set_error("");
   return SW_OK;
@@ -1842,6 +1924,10 @@ static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
       if (value != 0 && value != 2 && value != 4 && value != 8)
         return fail(SW_EINVAL, "intra rows must be 0, 2, 4 or 8");
       db->opt_intra_rows = (int32_t)value;
+      return SW_OK;
+    case SW_OPT_HYBRID_SHARE:
+      if (value < 0 || value > 1000) return fail(SW_EINVAL, "hybrid share must be in 0..1000");
+      db->hyb_share = (int32_t)value;
       return SW_OK;
     case SW_OPT_GRAPHS:
       if (value != 0 && value != 1) return fail(SW_EINVAL, "graphs must be 0 or 1");
