@@ -201,16 +201,21 @@ int sw_search_topk_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
  * sw_search_hybrid: one query against every database sequence with host
  * cores and the GPU at once (paper section 2.3: SW#db uses CPUs and GPUs
  * simultaneously with dynamic work distribution; the experiments of section
- * 4.1 give the CPU side one thread, T=1).  The short bins form one shared
- * work order, longest first: the calling thread launches the GPU's
- * inter-task kernel on chunks taken from the front (at most two chunks
- * queued, the next claimed when the earlier one ends), while `cpu_threads`
- * host threads (0: one fewer than the host's hardware threads) take single
- * bins from the back and score them with the host scorer (Farrar's striped
- * 16-bit SIMD recurrence with exact 32-bit rescoring, the code behind
- * sw_host_search); the two meet where their speeds balance.  Long sequences
- * and the GPU's rescoring stay on the GPU.  Scores are identical to
- * sw_search.  Host buffers, synchronous; `stats` may be NULL. */
+ * 4.1 give the CPU side one thread, T=1).  The short bins' sequences form
+ * one shared work order, longest first: the calling thread launches the
+ * GPU's inter-task kernel on chunks of whole bins taken from the front (at
+ * most two chunks queued, the next claimed when the earlier one ends),
+ * while `cpu_threads` host threads (0: one fewer than the host's hardware
+ * threads) take single sequences from the back and score them with the host
+ * scorer (Farrar's striped 16-bit SIMD recurrence with exact 32-bit
+ * rescoring, the code behind sw_host_search).  The split is planned from
+ * both sides' rates measured by earlier calls on the handle: the GPU's first
+ * chunk leaves the host twice its expected share, and a host thread gives
+ * back a sequence it would not finish by the planned end, so the GPU never
+ * waits long for the host; the bin where the two meet may be scored by
+ * both (with identical scores).  Long sequences and the GPU's rescoring
+ * stay on the GPU.  Scores are identical to sw_search.  Host buffers,
+ * synchronous; `stats` may be NULL. */
 typedef struct sw_hybrid_stats {
   int64_t gpu_bins;                /* short bins the GPU scored */
   int64_t cpu_seqs;                /* short sequences the host threads scored */

@@ -200,15 +200,18 @@ class Database:
             None if cache is None else str(cache).encode(), ctypes.byref(rep)))
         nb, nc, ni = _native.TUNE_BUCKETS, _native.TUNE_CANDIDATES, _native.TUNE_INTRA_CANDIDATES
         cands = [(rep.cand_rows[c], rep.cand_waves[c]) for c in range(nc)]
+        icands = [(rep.intra_cand_rows[c], rep.intra_cand_waves[c]) for c in range(ni)]
         out = []
         for b in range(nb):
             out.append({"query_len": rep.query_len[b],
                         "gcups": {"%dx%d" % cands[c]: rep.gcups[b][c] for c in range(nc)},
                         "batch_gcups": {"%dx%d" % cands[c]: rep.batch_gcups[b][c]
                                         for c in range(nc)},
+                        "intra_ms": {"%dx%d" % icands[c]: rep.intra_ms[b][c] for c in range(ni)},
                         "chosen": (rep.rows[b], rep.waves[b]),
-                        "batch_chosen": (rep.batch_rows[b], rep.batch_waves[b])})
-        return {"buckets": out}
+                        "batch_chosen": (rep.batch_rows[b], rep.batch_waves[b]),
+                        "intra_chosen": (rep.intra_rows[b], rep.intra_waves[b])})
+        return {"buckets": out, "from_cache": bool(rep.from_cache)}
 
     def search(self, query, matrix, gap_open: int = 10, gap_extend: int = 2) -> np.ndarray:
         """Scores of one query against every sequence (host in, host out)."""
