@@ -161,6 +161,32 @@ int sw_search_batch_async(sw_db* db, const uint8_t* d_queries, const int64_t* qu
                           int32_t n_queries, const int8_t* matrix, int32_t gap_open,
                           int32_t gap_extend, int32_t* d_out_scores, void* hip_stream);
 
+/* sw_search_async_noalloc: sw_search_async for callers that cannot allocate
+ * device memory - code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, layouts and scores as
+ * sw_search_async; it calls no hipMalloc, hipFree or other allocating
+ * routine.  Its scratch is one array of SW_NOALLOC_SCRATCH_BYTES per GPU,
+ * part of the library's code object: each GPU the library runs on holds it
+ * until the process ends (its address is looked up and its boundary-row
+ * part cleared when a database is first loaded on that GPU).  96 MiB of it
+ * take the inter-task boundary rows of the short bins, launched in chunks
+ * that fit (512 bytes per padded bin column); the rest takes the rescoring
+ * list (8 bytes per sequence), the query's profiles (about 300 bytes per
+ * query residue), and boundary rows of the long-sequence and rescoring
+ * kernels (8 bytes per residue of the longest sequence per workgroup; their
+ * grids shrink to what fits).  Calls that need more - a short bin longer
+ * than 196,608 residues, or fixed parts plus one row of each intra-task
+ * kernel beyond the array - return SW_ERANGE and enqueue nothing.
+ * Every call on a GPU shares that GPU's array and leaves it in the state the
+ * next call needs (zeros in the boundary-row part), so calls on one GPU must
+ * not overlap: issue them on one stream, or order them with events; calls
+ * that overlap on one GPU race and give wrong scores.  Timing (SW_OPT_TIMING)
+ * is not recorded for these calls. */
+#define SW_NOALLOC_SCRATCH_BYTES (128u << 20)
+int sw_search_async_noalloc(sw_db* db, const uint8_t* d_query, int32_t query_len,
+                            const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                            int32_t* d_out_scores, void* hip_stream);
+
 /* ------------------------------------------------------------------ top hits
  * sw_search_topk: one search (as sw_search) followed by its k best hits with
  * the end of each hit's best local alignment.  A search tool reports the

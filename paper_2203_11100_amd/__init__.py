@@ -231,6 +231,17 @@ class Database:
             self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
             _ptr(d_out), _stream_handle(stream)))
 
+    def search_async_noalloc(self, d_query, matrix, gap_open: int, gap_extend: int, d_out,
+                             stream=None):
+        """As search_async, allocating no device memory (sw_search_async_noalloc):
+        its scratch is the library's fixed per-GPU array, so calls on one GPU
+        must be ordered (one stream, or events) - overlapping ones race."""
+        _check_search_args(d_query, d_out, self.n_seqs)
+        m = _matrix(matrix)
+        _native.check(_native.lib().sw_search_async_noalloc(
+            self._h, _ptr(d_query), int(d_query.numel()), _ptr(m), gap_open, gap_extend,
+            _ptr(d_out), _stream_handle(stream)))
+
     def search_topk(self, query, matrix, gap_open: int = 10, gap_extend: int = 2, k: int = 10,
                     scores: bool = False):
         """The k best hits of one query (sw_search_topk): a structured array

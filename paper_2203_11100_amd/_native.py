@@ -24,6 +24,7 @@ SW_OPT_INTRA_WAVES = 6
 SW_OPT_GRAPHS = 7
 SW_OPT_HYBRID_SHARE = 8
 SW_MAX_TOPK = 4096
+SW_NOALLOC_SCRATCH_BYTES = 128 << 20
 SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1, 2
 
 _STATUS_NAMES = {1: "SW_EINVAL", 2: "SW_ERANGE", 3: "SW_ENOMEM", 4: "SW_EDEVICE", 5: "SW_EBUSY"}
@@ -88,6 +89,7 @@ SIGNATURES = {
     "sw_db_info": (ctypes.c_int, [P, P, P, P, P]),
     "sw_search": (ctypes.c_int, [P, P, I32, P, I32, I32, P]),
     "sw_search_async": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
+    "sw_search_async_noalloc": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
     "sw_search_topk": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P]),
     "sw_search_topk_async": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P, P]),
     "sw_search_hybrid": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P,

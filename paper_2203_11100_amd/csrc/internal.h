@@ -68,7 +68,8 @@ struct InterArgs {
   int32_t n_strips;           // query strips of R rows
   const uint32_t* prof;       // n_strips * prof_strip_dwords(R) dwords
   uint32_t go2, ge2;          // gap penalties (binary16, capped at 2048) in both halves
-  uint4* rb;                  // boundary-row buffers of all bins
+  uint4* rb;                  // boundary-row buffers: bin b's at rb + (rb_off(b) - rb_base)
+  int64_t rb_base;            // rb_off of the bin whose buffer starts at rb (0: all bins)
   const int32_t* slot_seq;
   int32_t* out;
   int32_t* flag_count;        // rescoring list: count, then {sid, query}

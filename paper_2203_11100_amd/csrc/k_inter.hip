@@ -87,7 +87,7 @@ __global__ __launch_bounds__(64 * W) void k_inter_f16(InterArgs a) {
   __syncthreads();
 
   const uint2* __restrict__ rbin = a.res2 + (bin.res_off >> 1);
-  uint4* __restrict__ rbb = a.rb + bin.rb_off;
+  uint4* __restrict__ rbb = a.rb + (bin.rb_off - a.rb_base);
   const uint32_t go = a.go2, ge = a.ge2;
 
   // inputs of the next chunk, fetched one superstep ahead.  The first strip

@@ -735,7 +735,7 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
       grid = X.grid_seg;
     }
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
-    if ((e = launch_intra_pairs(RR, W2, X.grid_long, la, db->aux_stream)) != hipSuccess)
+    if ((e = launch_intra_pairs(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "intra-task kernel");
     db->stats.long_items = la.count;
     db->stats.long_overlap = segmented ? overlap : -1;
@@ -1249,6 +1249,126 @@ int run_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, int3
 }  // namespace
 }  // namespace swdb
 
+// ------------------------------------------------- allocation-free search
+// Scratch of sw_search_async_noalloc: one array per GPU, part of the
+// library's code object, so every GPU the library runs on holds it until the
+// process ends.  On the host the array's name is only a stand-in; host code
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, looked up once per device (noalloc_setup) and kept in g_noalloc.
+//
+// Layout: the first kNoAllocRowBytes hold the inter-task boundary rows of one
+// chunk of short bins at a time.  That part holds zeros between calls: it is
+// cleared at set-up, and the last strip of every bin writes zeros back over
+// its rows, as in the handle's own boundary buffer.  The rest is laid out per
+// call (noalloc_layout): rescoring list, the three profiles, the rescoring
+// kernel's rows and the long-sequence kernel's rows; none of it has to start
+// at zero (the profile kernel clears the list's count, and the intra-task
+// kernels read a boundary row only after a pass has written it).
+static __device__ __align__(256) uint8_t scratch[SW_NOALLOC_SCRATCH_BYTES];
+
+namespace swdb {
+namespace {
+
+constexpr size_t kNoAllocRowBytes = size_t(96) << 20;
+static_assert(SW_NOALLOC_SCRATCH_BYTES > kNoAllocRowBytes + (size_t(1) << 20),
+              "the allocation-free scratch needs room beside the boundary rows");
+constexpr int kNoAllocMaxDevices = 64;
+
+struct NoAllocDevice {
+  uint8_t* ptr = nullptr;   // this device's copy of `scratch`
+};
+std::mutex g_noalloc_mu;
+NoAllocDevice g_noalloc[kNoAllocMaxDevices];
+
+// Looks up device `device`'s copy of the scratch array and clears its
+// boundary-row part, once per device; the device must be current.
+int noalloc_setup(int device, uint8_t** out) {
+  if (device < 0 || device >= kNoAllocMaxDevices)
+    return fail(SW_ERANGE, "allocation-free search: device index above 63");
+  std::lock_guard<std::mutex> l(g_noalloc_mu);
+  NoAllocDevice& nd = g_noalloc[device];
+  if (!nd.ptr) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "scratch address");
+    // a fill kernel, then wait: set-up happens once, before any search uses it
+    if ((e = launch_fill(reinterpret_cast<int32_t*>(p), (int64_t)(kNoAllocRowBytes / 4), 0,
+                         nullptr)) != hipSuccess ||
+        (e = hipStreamSynchronize(nullptr)) != hipSuccess)
+      return hip_fail(e, "scratch clear");
+    nd.ptr = reinterpret_cast<uint8_t*>(p);
+  }
+  *out = nd.ptr;
+  return SW_OK;
+}
+
+// Where one allocation-free search keeps its scratch inside the array at
+// `base`, and the grids the long-list and rescoring kernels get there.
+struct NoAllocLayout {
+  SearchScratch X;
+  size_t bytes = 0;   // end of the per-call part
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int noalloc_layout(const Searcher* db, const SearchShape& sh, uint8_t* base, NoAllocLayout* L) {
+  const Plan& P = db->d->plan;
+  if ((size_t)P.max_bin_len * 512 > kNoAllocRowBytes)
+    return fail(SW_ERANGE, "allocation-free search: a short bin's boundary rows (" +
+                               std::to_string((size_t)P.max_bin_len * 512) +
+                               " bytes) exceed the 96 MiB chunk");
+  const ScratchSizes z = scratch_sizes(db, sh, 0, 0);
+  size_t at = kNoAllocRowBytes;
+  auto take = [&](size_t bytes) {
+    const size_t o = at;
+    at = align256(at + bytes);
+    return base + o;
+  };
+  L->X.rb = reinterpret_cast<uint4*>(base);
+  L->X.flags = reinterpret_cast<int32_t*>(take(z.flags * 4));
+  L->X.prof = reinterpret_cast<uint32_t*>(take(z.prof * 4));
+  L->X.prof2 = reinterpret_cast<int8_t*>(take(z.prof2));
+  L->X.prof3 = P.n_long > 0 ? reinterpret_cast<uint32_t*>(take(z.prof3 * 4)) : nullptr;
+  L->X.seg_best =
+      P.n_long > 0 ? reinterpret_cast<uint32_t*>(take((size_t)db->d->n_seg_items * 4)) : nullptr;
+  // one boundary row per workgroup of the rescoring and long-list kernels;
+  // both loop over their items, so a smaller grid only takes more rounds
+  const size_t resc_row = align256((size_t)rescore_stride(P) * sizeof(int2));
+  const size_t long_row =
+      P.n_long > 0 ? align256((size_t)std::max<int32_t>(P.max_long_len, 1) * sizeof(int2)) : 0;
+  const size_t total = (size_t)SW_NOALLOC_SCRATCH_BYTES;
+  if (at + resc_row + long_row > total)
+    return fail(SW_ERANGE, "allocation-free search needs " +
+                               std::to_string(at + resc_row + long_row) +
+                               " bytes of scratch, more than SW_NOALLOC_SCRATCH_BYTES (" +
+                               std::to_string(total) + ")");
+  const size_t avail = total - at;
+  // rescoring (usually an empty list) gets up to an eighth of what is left,
+  // the long list the rest
+  size_t grid_resc = std::max<size_t>(
+      1, std::min<size_t>({avail / 8 / resc_row, (size_t)kIntraGridRescore, 64}));
+  while (grid_resc > 1 && grid_resc * resc_row + long_row > avail) --grid_resc;
+  L->X.rb_resc = reinterpret_cast<int2*>(take(grid_resc * resc_row));
+  L->X.grid_resc = (int)grid_resc;
+  int grid_long = 0;
+  if (P.n_long > 0) {
+    const size_t left = total - at;   // >= long_row by the checks above
+    grid_long = (int)std::max<size_t>(
+        1, std::min<size_t>({left / long_row, (size_t)db->d->n_long_pairs, (size_t)kIntraGridLong}));
+    L->X.rb_long = reinterpret_cast<int2*>(take((size_t)grid_long * long_row));
+    // the same rows serve the column segments, at their shorter stride
+    L->X.grid_seg = (int)std::min<size_t>(
+        {(size_t)grid_long * long_row / ((size_t)seg_stride(*db->d) * sizeof(int2)),
+         (size_t)db->d->n_seg_items, (size_t)kIntraGridLong});
+  }
+  L->X.grid_long = grid_long;
+  L->bytes = at;
+  return SW_OK;
+}
+
+}  // namespace
+}  // namespace swdb
+
 extern "C" {
 
 int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seqs,
@@ -1368,6 +1488,12 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
     destroy_db(h);
     set_error(msg);
     return rc;
+  }
+  {
+    // set-up of the allocation-free search's scratch on this device (a
+    // failure here is reported by that entry point, which retries it)
+    uint8_t* na = nullptr;
+    (void)noalloc_setup(d->device, &na);
   }
   *out_db = h;
   set_error("");
@@ -1819,6 +1945,71 @@ static int impl_search_mode(swdb::Searcher* db, const uint8_t* query, int32_t qu
   return SW_OK;
 }
 
+static int impl_search_async_noalloc(swdb::Searcher* db, const uint8_t* d_query,
+                                     int32_t query_len, const int8_t* matrix, int32_t gap_open,
+                                     int32_t gap_extend, int32_t* d_out_scores,
+                                     void* hip_stream) {
+  using namespace swdb;
+  int rc = validate_search(db, d_query, query_len, matrix, gap_open, gap_extend, d_out_scores);
+  if (rc != SW_OK) return rc;
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  uint8_t* base = nullptr;
+  if ((rc = noalloc_setup(db->d->device, &base)) != SW_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  const DbData& D = *db->d;
+  hipError_t e;
+  if (D.n_seqs == 0) {
+    set_error("");
+    return SW_OK;
+  }
+  if (query_len == 0) {
+    if ((e = launch_fill(d_out_scores, D.n_seqs, 0, s)) != hipSuccess) return hip_fail(e, "fill");
+    mark_caller_work(db, s);
+    set_error("");
+    return SW_OK;
+  }
+  const SearchShape sh = search_shape(db, query_len);
+  NoAllocLayout L;
+  if ((rc = noalloc_layout(db, sh, base, &L)) != SW_OK) return rc;
+  // the short bins in chunks whose boundary rows fit the 96 MiB part; each
+  // chunk's rows start at the array's start (rb_base = the chunk's first
+  // rb_off), and launches on one stream run one after the other
+  const int64_t* hb = D.h_bins.data();   // {res_off, rb_off, len, slot0} per bin
+  const int64_t n_bins = D.plan.n_bins;
+  BinRunner runner = [&](InterArgs& a, int R, int W, hipStream_t st) -> int {
+    for (int64_t b0 = 0; b0 < n_bins;) {
+      const int64_t first = hb[4 * b0 + 1];
+      int64_t b1 = b0 + 1;
+      while (b1 < n_bins &&
+             (size_t)(hb[4 * b1 + 1] + 32 * hb[4 * b1 + 2] - first) * sizeof(uint4) <=
+                 kNoAllocRowBytes)
+        ++b1;
+      a.bin_begin = (int32_t)b0;
+      a.rb = L.X.rb;
+      a.rb_base = first;
+      hipError_t err;
+      if ((err = launch_inter(R, W, (int)(b1 - b0), a, st)) != hipSuccess)
+        return hip_fail(err, "inter-task kernel");
+      ++db->stats.n_inter_launches;
+      b0 = b1;
+    }
+    return SW_OK;
+  };
+  Matrix mat;
+  memcpy(mat.v, matrix, sizeof(mat.v));
+  // no timing events here: recording them may create events
+  const bool timing = db->timing;
+  db->timing = false;
+  rc = enqueue_search_kernels(db, sh, L.X, d_query, query_len, mat, gap_open, gap_extend,
+                              d_out_scores, s, &runner);
+  db->timing = timing;
+  mark_caller_work(db, s);
+  if (rc == SW_OK) set_error("");
+  return rc;
+}
+
 static int validate_batch(const swdb::Searcher* db, const void* queries, const int64_t* qoffs, int32_t nq,
                           const int8_t* matrix, int32_t go, int32_t ge, const void* out) {
   using namespace swdb;
@@ -2260,6 +2451,12 @@ int sw_search_async(sw_db* h, const uint8_t* d_query, int32_t query_len, const i
                     int32_t gap_open, int32_t gap_extend, int32_t* d_out_scores, void* hip_stream) {
   return impl_search_async(S_of(h), d_query, query_len, matrix, gap_open, gap_extend, d_out_scores,
                            hip_stream);
+}
+int sw_search_async_noalloc(sw_db* h, const uint8_t* d_query, int32_t query_len,
+                            const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                            int32_t* d_out_scores, void* hip_stream) {
+  return impl_search_async_noalloc(S_of(h), d_query, query_len, matrix, gap_open, gap_extend,
+                                   d_out_scores, hip_stream);
 }
 int sw_search_topk(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
                    int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* out_scores,
