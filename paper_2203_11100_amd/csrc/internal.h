@@ -83,6 +83,9 @@ struct QueryDesc {
   int64_t out_off;            // offset of the query's score row in `out`
   int32_t m_pad2;             // profile row length: a multiple of 64*R
   int32_t n_pass;             // passes of 64*R rows covering the query
+  int64_t prof3_off;          // dword offset of its packed [25][m_pad2 / 2] profile (batches)
+  int32_t n_pass3;            // passes of the packed long-pair kernel (its own R)
+  int32_t pad_;
 };
 
 struct IntraArgs {
@@ -147,6 +150,11 @@ struct IntraPairArgs {
   const int2* seg_items;
   int32_t seg_cols, seg_overlap;
   uint32_t* seg_best;
+  // batches: with batch_items non-null, item x is {pair index into items,
+  // query}, and the query's packed profile, pass count and score row come
+  // from queries[query] (prof3 then points at all queries' profiles)
+  const int2* batch_items;
+  const QueryDesc* queries;
 };
 
 // Batched inter-task kernel: the two 16-bit halves of a lane hold two
@@ -227,10 +235,11 @@ hipError_t launch_topk(const int32_t* scores, int64_t n, int32_t k, TopkState* s
 // hits[i] = {items[i].x, 0, -1, -1}: the hit list of an empty query.
 hipError_t launch_empty_hits(const int2* items, int32_t k, int4* hits, hipStream_t s);
 // Pair profiles for `n_pairs` pairs and intra-task profiles for `n_queries`
-// queries of a batch (see k_misc.hip for the layouts).
+// queries of a batch (see k_misc.hip for the layouts); prof3 (or nullptr)
+// receives the queries' packed long-pair profiles.
 hipError_t launch_batch_profiles(const uint8_t* d_queries, const int64_t* d_qoffs, int n_queries,
                                  const Matrix& mat, const PairDesc* d_pairs, int n_pairs, int R,
                                  int64_t max_work, uint32_t* prof, const QueryDesc* d_qdesc,
-                                 int8_t* prof2, hipStream_t s);
+                                 int8_t* prof2, uint32_t* prof3, hipStream_t s);
 
 }  // namespace swdb

@@ -368,13 +368,24 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
   const char* lbase = reinterpret_cast<const char*>(lprof) + lane * RP * 4;
   int2* __restrict__ rb = a.scratch + (size_t)blockIdx.x * a.scratch_stride;
   const uint32_t go = a.go2, ge = a.ge2;
-  const int P = a.n_pass;
-  const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
-  const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
 
   for (int it = blockIdx.x; it < a.count; it += gridDim.x) {
     const int2 seg = a.seg_items ? a.seg_items[it] : make_int2(it, 0);
-    const int2 item = a.items[seg.x];
+    // the query: the search's, or (batches) the item's own
+    const int2 bitem = a.batch_items ? a.batch_items[it] : make_int2(seg.x, 0);
+    const uint32_t* __restrict__ prof3 = a.prof3;
+    int m_pad2 = a.m_pad2, P = a.n_pass;
+    int64_t out_off = 0;
+    if (a.batch_items) {
+      const QueryDesc qd = a.queries[bitem.y];
+      prof3 += qd.prof3_off;
+      m_pad2 = qd.m_pad2;
+      P = qd.n_pass3;
+      out_off = qd.out_off;
+    }
+    const int q_last = (P - 1) / W2, w_last = (P - 1) % W2;
+    const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
+    const int2 item = a.items[bitem.x];
     const int sa = item.x, sb = item.y;
     const int64_t ba = a.offs[sa];
     int na = (int)(a.offs[sa + 1] - ba);
@@ -427,10 +438,10 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
       const bool more = q + 1 < my_rounds;
       const bool last_pass = p == P - 1;
       {  // stage this pass's profile row pairs (read back only by this wave)
-        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(a.prof3);
+        const uint4* __restrict__ src = reinterpret_cast<const uint4*>(prof3);
         uint4* dst = reinterpret_cast<uint4*>(lprof);
         constexpr int per_code = CODE_DW / 4;          // uint4 per code row
-        const int src_stride = a.m_pad2 / 8;           // uint4 per code in prof3
+        const int src_stride = m_pad2 / 8;             // uint4 per code in prof3
         for (int x = lane; x < kIntraCodes * per_code; x += 64) {
           const int code = x / per_code, r = x - code * per_code;
           dst[x] = src[(size_t)code * src_stride + (size_t)p * per_code + r];
@@ -524,9 +535,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
         const int score = half_score(b, half, a.sat_limit);
         if (score < 0) {
           const int idx = atomicAdd(a.flag_count, 1);
-          a.flag_list[idx] = make_int2(sid, 0);
+          a.flag_list[idx] = make_int2(sid, bitem.y);
         } else {
-          a.out[sid] = score;
+          a.out[out_off + sid] = score;
         }
       }
     }

@@ -57,12 +57,14 @@ __global__ void k_profile(const uint8_t* __restrict__ q, int m, Matrix mat,
 // selects a pair: the dword of row i and code c of its profile (n_strips * R
 // rows in the kProfRowDwords layout) holds (S(a_i, c), S(b_i, c)) as
 // binary16, kPadScore past either query's end.  Larger
-// blockIdx.y select a query's intra-task [25][m_pad2] int8 profile.
+// blockIdx.y select a query's intra-task [25][m_pad2] int8 profile and, when
+// prof3 is given, its packed [25][m_pad2 / 2] binary16 row pairs.
 __global__ void k_batch_profiles(const uint8_t* __restrict__ queries,
                                  const int64_t* __restrict__ qoffs, Matrix mat,
                                  const PairDesc* __restrict__ pairs, int n_pairs, int R,
                                  uint32_t* __restrict__ prof,
-                                 const QueryDesc* __restrict__ qdesc, int8_t* __restrict__ prof2) {
+                                 const QueryDesc* __restrict__ qdesc, int8_t* __restrict__ prof2,
+                                 uint32_t* __restrict__ prof3) {
   const int y = blockIdx.y;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,6 +91,15 @@ __global__ void k_batch_profiles(const uint8_t* __restrict__ queries,
     for (int64_t idx = start; idx < total; idx += stride) {
       const int c = (int)(idx / qd.m_pad2), i = (int)(idx % qd.m_pad2);
       prof2[qd.prof2_off + idx] = (int8_t)profile_score(q, m, mat, i, c);
+    }
+    if (prof3) {   // packed binary16 row pairs [25][m_pad2 / 2] (the layout of k_profile)
+      const int half_rows = qd.m_pad2 / 2;
+      for (int64_t idx = start; idx < (int64_t)kIntraCodes * half_rows; idx += stride) {
+        const int c = (int)(idx / half_rows), r = (int)(idx % half_rows);
+        const uint32_t lo = half_bits(profile_score(q, m, mat, 2 * r, c));
+        const uint32_t hi = half_bits(profile_score(q, m, mat, 2 * r + 1, c));
+        prof3[qd.prof3_off + idx] = lo | (hi << 16);
+      }
     }
   }
 }
@@ -117,13 +128,13 @@ hipError_t launch_profile(const uint8_t* d_query, int m, const Matrix& mat, uint
 hipError_t launch_batch_profiles(const uint8_t* d_queries, const int64_t* d_qoffs, int n_queries,
                                  const Matrix& mat, const PairDesc* d_pairs, int n_pairs, int R,
                                  int64_t max_work, uint32_t* prof, const QueryDesc* d_qdesc,
-                                 int8_t* prof2, hipStream_t s) {
+                                 int8_t* prof2, uint32_t* prof3, hipStream_t s) {
   const int ys = n_pairs + n_queries;
   if (ys <= 0) return hipSuccess;
   if (ys > 65535) return hipErrorInvalidValue;
   const int gx = (int)std::max<int64_t>(1, std::min<int64_t>((max_work + 255) / 256, 256));
   hipLaunchKernelGGL(k_batch_profiles, dim3(gx, ys), dim3(256), 0, s, d_queries, d_qoffs, mat,
-                     d_pairs, n_pairs, R, prof, d_qdesc, prof2);
+                     d_pairs, n_pairs, R, prof, d_qdesc, prof2, prof3);
   return hipGetLastError();
 }
 

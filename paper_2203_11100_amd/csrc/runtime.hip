@@ -118,7 +118,7 @@ struct BatchPlan {
   int32_t go = 0, ge = 0, sat_limit = 0;
   const uint8_t* d_queries = nullptr;
   int32_t* d_out = nullptr;
-  int R = 0, W = 0, RR = 0, W2 = 0, W2r = 0;
+  int R = 0, W = 0, RR = 0, W2 = 0, W2r = 0, RRp = 0, W2p = 0;
   int n_pairs = 0;
   int64_t n_items = 0, n_long_items = 0, max_pair_work = 0, max_query_work = 0;
   int64_t inter_cells = 0, intra_cells = 0;
@@ -126,10 +126,14 @@ struct BatchPlan {
   std::vector<int32_t> zero_queries;
   swdb::DevBuf<swdb::PairDesc> pairs;
   swdb::DevBuf<swdb::QueryDesc> qdesc;
-  swdb::DevBuf<int2> items, long_items;
+  swdb::DevBuf<int2> items;
+  // the very long sequences in pairs, and the (pair, query) items of the
+  // packed long-pair kernel, costliest first
+  swdb::DevBuf<int2> vpairs, long_items;
   swdb::DevBuf<int64_t> qoffs_d;
   swdb::DevBuf<uint32_t> prof;
   swdb::DevBuf<int8_t> prof2;
+  swdb::DevBuf<uint32_t> prof3;     // the queries' packed long-pair profiles
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // the searcher's scratch buffers the captured graph's kernels address
@@ -147,7 +151,7 @@ struct BatchPlan {
   void release() {
     drop_graph();
     pairs.release(); qdesc.release(); items.release(); long_items.release();
-    qoffs_d.release(); prof.release(); prof2.release();
+    vpairs.release(); qoffs_d.release(); prof.release(); prof2.release(); prof3.release();
     valid = false;
   }
 };
@@ -303,7 +307,8 @@ void bind_buffers(Searcher* S) {
   S->mprof.users = S->rb_mode.users = u;
   BatchPlan& B = S->batch;
   B.pairs.users = u; B.qdesc.users = u; B.items.users = u; B.long_items.users = u;
-  B.qoffs_d.users = u; B.prof.users = u; B.prof2.users = u;
+  B.vpairs.users = u; B.qoffs_d.users = u; B.prof.users = u; B.prof2.users = u;
+  B.prof3.users = u;
 }
 
 // Per-workgroup boundary-row length of the rescoring launch: any sequence of
@@ -1024,21 +1029,27 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
     B.max_pair_work = std::max<int64_t>(B.max_pair_work, (int64_t)pd.n_strips * R * kBatchRowDwords);
     pairs.push_back(pd);
   }
-  // intra-task parameters from the median query length
+  // intra-task parameters from the median query length: the 32-bit
+  // kernel's (rescoring) and the packed long-pair kernel's
   const int64_t m_med = n_nz ? ms[order[n_nz / 2]] : 1;
-  int RR = 8, W2 = 1, RRd = 8, W2r = 1;
+  int RR = 8, W2 = 1, RRd = 8, W2r = 1, RRp = 8, W2p = 1;
   pick_intra(db, (int)m_med, 8, &RR, &W2);
   pick_intra(db, (int)m_med, 2, &RRd, &W2r);
+  pick_intra(db, (int)m_med, 8, &RRp, &W2p, true);
   (void)RRd;
+  const bool has_vlong = db->d->plan.n_vlong > 0;
   std::vector<QueryDesc> qd((size_t)std::max(nq, 1));
-  int64_t prof2_bytes = 0;
+  int64_t prof2_bytes = 0, prof3_dw = 0;
   for (int32_t q = 0; q < nq; ++q) {
     const int64_t m = std::max<int64_t>(ms[q], 1);
     qd[q].m_pad2 = (int32_t)((m + 511) / 512 * 512);
     qd[q].n_pass = (int32_t)((m + 64 * RR - 1) / (64 * RR));
+    qd[q].n_pass3 = (int32_t)((m + 64 * RRp - 1) / (64 * RRp));
     qd[q].prof2_off = prof2_bytes;
+    qd[q].prof3_off = prof3_dw;
     qd[q].out_off = (int64_t)q * db->d->n_seqs;
     prof2_bytes += (int64_t)kIntraCodes * qd[q].m_pad2;
+    if (has_vlong) prof3_dw += (int64_t)kIntraCodes * (qd[q].m_pad2 / 2);
     if (ms[q] > 0) B.max_query_work = std::max<int64_t>(B.max_query_work, (int64_t)kIntraCodes * qd[q].m_pad2);
   }
   // (pair, half bin) items, costliest first
@@ -1056,14 +1067,17 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
   };
   std::stable_sort(items.begin(), items.end(),
                    [&](const int2& a, const int2& b) { return cost(a) > cost(b); });
-  // (very long sequence, query) items, costliest first
+  // the very long sequences (longest first) in pairs of neighbours, and
+  // (pair, query) items for the packed long-pair kernel, costliest first
+  std::vector<int2> vpairs;
+  for (int64_t t = 0; t < db->d->plan.n_vlong; t += 2)
+    vpairs.push_back(make_int2(db->d->long_ids[(size_t)t],
+                               t + 1 < db->d->plan.n_vlong ? db->d->long_ids[(size_t)t + 1] : -1));
   std::vector<int2> litems;
-  for (int64_t t = 0; t < db->d->plan.n_vlong; ++t)
-    for (int32_t q : order) litems.push_back(make_int2(db->d->long_ids[(size_t)t], q));
-  const int64_t* offs = nullptr;
-  (void)offs;
+  for (int p = 0; p < (int)vpairs.size(); ++p)
+    for (int32_t q : order) litems.push_back(make_int2(p, q));
   auto lcost = [&](const int2& it) {
-    return ms[it.y] * (int64_t)db->d->long_len[(size_t)it.x];
+    return ms[it.y] * (int64_t)db->d->long_len[(size_t)vpairs[(size_t)it.x].x];
   };
   std::stable_sort(litems.begin(), litems.end(),
                    [&](const int2& a, const int2& b) { return lcost(a) > lcost(b); });
@@ -1080,6 +1094,8 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
       (e = B.qdesc.reserve(qd.size())) != hipSuccess ||
       (e = B.items.reserve(std::max<size_t>(items.size(), 1))) != hipSuccess ||
       (e = B.long_items.reserve(std::max<size_t>(litems.size(), 1))) != hipSuccess ||
+      (e = B.vpairs.reserve(std::max<size_t>(vpairs.size(), 1))) != hipSuccess ||
+      (e = B.prof3.reserve((size_t)std::max<int64_t>(prof3_dw, 4))) != hipSuccess ||
       (e = B.qoffs_d.reserve(qv.size())) != hipSuccess ||
       (e = B.prof.reserve((size_t)std::max<int64_t>(prof_dw, 1))) != hipSuccess ||
       (e = B.prof2.reserve((size_t)std::max<int64_t>(prof2_bytes, 16))) != hipSuccess)
@@ -1088,6 +1104,7 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
       (e = put(B.qdesc.p, qd.data(), qd.size() * sizeof(QueryDesc))) != hipSuccess ||
       (e = put(B.items.p, items.data(), items.size() * sizeof(int2))) != hipSuccess ||
       (e = put(B.long_items.p, litems.data(), litems.size() * sizeof(int2))) != hipSuccess ||
+      (e = put(B.vpairs.p, vpairs.data(), vpairs.size() * sizeof(int2))) != hipSuccess ||
       (e = put(B.qoffs_d.p, qv.data(), qv.size() * sizeof(int64_t))) != hipSuccess)
     return hip_fail(e, "batch descriptors");
   B.n_pairs = (int)pairs.size();
@@ -1098,13 +1115,15 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
   B.RR = RR;
   B.W2 = W2;
   B.W2r = W2r;
+  B.RRp = RRp;
+  B.W2p = W2p;
   B.grid_b = db->d->n_cus * batch_workgroups_per_cu(R, W);
   B.grid_long = (int)std::min<int64_t>(B.n_long_items, kIntraGridLong);
   if ((e = db->rb_batch.reserve((size_t)B.grid_b * (size_t)(db->d->plan.max_all_bin_len / 4) * 128)) !=
           hipSuccess ||
       (e = db->counter.reserve(1)) != hipSuccess ||
-      (e = reserve_flags(db, ((db->d->plan.n_bins + db->d->plan.n_long_bins) * (int64_t)SW_BIN_SEQS) *
-                                 std::max(n_nz, 1))) != hipSuccess ||
+      (e = reserve_flags(db, ((db->d->plan.n_bins + db->d->plan.n_long_bins) * (int64_t)SW_BIN_SEQS +
+                              db->d->plan.n_vlong) * std::max(n_nz, 1))) != hipSuccess ||
       (e = reserve_long_scratch(db, std::max(B.grid_long, 1))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("batch scratch: ") + hipGetErrorString(e));
   B.qoffs = qv;
@@ -1136,7 +1155,8 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
   }
   if ((e = launch_batch_profiles(B.d_queries, B.qoffs_d.p, nq, B.mat, B.pairs.p, B.n_pairs, B.R,
                                  std::max(B.max_pair_work, B.max_query_work), B.prof.p, B.qdesc.p,
-                                 B.prof2.p, s)) != hipSuccess)
+                                 B.prof2.p, B.n_long_items > 0 ? B.prof3.p : nullptr, s)) !=
+      hipSuccess)
     return hip_fail(e, "batch profiles");
   IntraArgs ia{};
   ia.res = db->d->res.p;
@@ -1149,15 +1169,30 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
   // Very long sequences first, on the same stream: the persistent batched
   // kernel holds every CU until its list is drained, so a concurrent launch
   // would only get CUs at the end.  These items are few and run in parallel.
+  // The very long sequences go in pairs through the packed long-pair
+  // kernel (binary16, two sequences per lane), each item with its query's
+  // profile and score row; sequences at the rescoring limit join the list
+  // the batched kernel fills.
   if (B.n_long_items > 0) {
-    IntraArgs la = ia;
-    la.items = B.long_items.p;
+    IntraPairArgs la{};
+    la.res = db->d->res.p;
+    la.offs = db->d->offs.p;
+    la.items = B.vpairs.p;
+    la.batch_items = B.long_items.p;
+    la.queries = B.qdesc.p;
     la.count = (int32_t)B.n_long_items;
+    la.prof3 = B.prof3.p;
+    la.go2 = half_pair(B.go);
+    la.ge2 = half_pair(B.ge);
+    la.sat_limit = effective_limit(B.sat_limit);
     la.scratch = db->rb_long.p;
     la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
+    la.out = B.d_out;
+    la.flag_count = db->flags.p;
+    la.flag_list = flag_list(db);
     const int tl = time_begin(db, kTimeIntra, s);
-    if ((e = launch_intra(B.RR, B.W2, B.grid_long, la, s)) != hipSuccess)
-      return hip_fail(e, "intra-task kernel");
+    if ((e = launch_intra_pairs(B.RRp, B.W2p, B.grid_long, la, s)) != hipSuccess)
+      return hip_fail(e, "long-pair kernel");
     time_end(db, tl, s);
   }
   if (db->d->plan.n_bins + db->d->plan.n_long_bins > 0) {
@@ -1183,6 +1218,8 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
     if ((e = launch_batch(B.R, B.W, B.grid_b, ba, s)) != hipSuccess)
       return hip_fail(e, "batched inter-task kernel");
     time_end(db, ti, s);
+  }
+  {  // exact rescoring of what both packed kernels flagged
     IntraArgs ra = ia;
     ra.items = flag_list(db);
     ra.count_ptr = db->flags.p;

@@ -509,6 +509,27 @@ def test_batch_long_and_rescoring_items(sw):
             assert (row == _oracle(q, res, offs)).all(), (t_long, limit)
 
 
+def test_batch_all_sequences_very_long(sw):
+    """Every sequence in the very-long list (no bins at all): a batch runs
+    only the packed long-pair kernel, with each item's own query, and the
+    rescoring; an odd count leaves one pair with an empty half; forced
+    rescoring (limit 0) and the full exact range."""
+    rng = np.random.default_rng(28)
+    lengths = rng.integers(100, 1500, 41).astype(np.int64)
+    res, offs = swinputs.make_database(lengths, rng)
+    qs = _queries(29, [60, 700, 1300, 0, 2500])
+    info = sw.plan(offs, 1)
+    assert info["n_bins"] == 0 and info["n_long_bins"] == 0 and info["n_very_long"] == 41
+    say("batch, every sequence very long")
+    for limit in (32767, 0):
+        with sw.Database(res, offs, long_threshold=1) as db:
+            db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
+            got = db.search_batch(qs, B62, 10, 2)
+        for q, row in zip(qs, got):
+            want = _oracle(q, res, offs) if len(q) else np.zeros(len(lengths), np.int32)
+            assert (row == want).all(), (limit, len(q))
+
+
 def test_batch_graph_replays_with_eager_work_between(sw):
     """Replays of the captured batch graph, with single searches and host
     synchronisation between them, each equal to the oracle.  The single
