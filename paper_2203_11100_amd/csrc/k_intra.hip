@@ -330,9 +330,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
 }
 
 template <int RP> struct PairVec;
-template <> struct PairVec<1> { typedef uint32_t T; static constexpr int n = 1; };
-template <> struct PairVec<2> { typedef uint2 T; static constexpr int n = 2; };
-template <> struct PairVec<4> { typedef uint4 T; static constexpr int n = 4; };
+template <> struct PairVec<1> { typedef uint32_t T; };
+template <> struct PairVec<2> { typedef uint2 T; };
+template <> struct PairVec<4> { typedef uint4 T; };
 __device__ __forceinline__ uint32_t pv_get(const uint32_t& v, int) { return v; }
 __device__ __forceinline__ uint32_t pv_get(const uint2& v, int j) { return j ? v.y : v.x; }
 __device__ __forceinline__ uint32_t pv_get(const uint4& v, int j) {

@@ -581,7 +581,9 @@ SearchShape search_shape(const Searcher* db, int m) {
   sh.n_strips = sh.m_pad / sh.R;
   sh.RR = 8; sh.W2 = 1; sh.RRr = 8; sh.W2r = 1;
   pick_intra(db, m, 8, &sh.RR, &sh.W2, true);   // long sequences, in pairs (binary16)
-  pick_intra(db, m, 2, &sh.RRr, &sh.W2r);       // exact rescoring (usually empty)
+  // exact rescoring (usually a few sequences, each the only one on its CU,
+  // so the latency of one sequence is what counts)
+  pick_intra(db, m, 8, &sh.RRr, &sh.W2r);
   // the intra-task profiles serve every intra-task launch of the query (long
   // list, rescoring, hit ends): pad to the largest pass, 64 x 8 rows
   sh.m_pad2 = intra_rows_pad(m);
@@ -1030,13 +1032,13 @@ int prepare_batch(Searcher* db, const uint8_t* d_queries, const int64_t* qoffs, 
     pairs.push_back(pd);
   }
   // intra-task parameters from the median query length: the 32-bit
-  // kernel's (rescoring) and the packed long-pair kernel's
+  // kernel's (long sequences of the i32 form, rescoring) and the packed
+  // long-pair kernel's
   const int64_t m_med = n_nz ? ms[order[n_nz / 2]] : 1;
-  int RR = 8, W2 = 1, RRd = 8, W2r = 1, RRp = 8, W2p = 1;
+  int RR = 8, W2 = 1, RRp = 8, W2p = 1;
   pick_intra(db, (int)m_med, 8, &RR, &W2);
-  pick_intra(db, (int)m_med, 2, &RRd, &W2r);
   pick_intra(db, (int)m_med, 8, &RRp, &W2p, true);
-  (void)RRd;
+  const int W2r = W2;
   const bool has_vlong = db->d->plan.n_vlong > 0;
   std::vector<QueryDesc> qd((size_t)std::max(nq, 1));
   int64_t prof2_bytes = 0, prof3_dw = 0;

@@ -3,16 +3,20 @@
 Runs, in one process:
   1. a plain device-to-device copy of COPY_MIB MiB (torch), the calibration
      kernel of known traffic: COPY_MIB MiB read and COPY_MIB MiB written;
-  2. the plain benchmark workload's searches for the chosen queries (default:
-     all 20), with the database already resident; with --long-only, the same
-     queries against a database of only the plain database's long sequences
-     (2,048 residues or more), so the long-sequence kernel runs alone.
+  2. a benchmark workload's searches for the chosen queries (default: all;
+     --workload plain, the 20-query plain workload, or long-mix, its 10
+     queries against the long-sequence mix), with the database already
+     resident; with --long-only, the plain queries against a database of only
+     the plain database's long sequences (2,048 residues or more), so the
+     long-sequence kernel runs alone.  --timing adds each search's kernel
+     times (HIP events) to the printed record.
 
 Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
 block per run) each dispatch gets its counter value; dividing a search
 kernel's value by the copy kernel's value per MiB converts it into bytes.
 
-    python pmc.py [--queries 0,19] [--copy-mib 1024] [--long-only] [--repeat N]
+    python pmc.py [--workload plain|long-mix] [--queries 0,19] [--copy-mib 1024]
+                  [--long-only] [--repeat N] [--timing]
 """
 import argparse
 import json
@@ -32,6 +36,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
     ap.add_argument("--long-only", action="store_true")
     ap.add_argument("--repeat", type=int, default=1)
+    ap.add_argument("--workload", default="plain", choices=("plain", "long-mix"))
+    ap.add_argument("--timing", action="store_true")
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -44,7 +50,7 @@ def main():
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
-    w = swinputs.config("plain")
+    w = swinputs.config(args.workload)
     idx = range(len(w.queries)) if args.queries == "all" else [int(x) for x in args.queries.split(",")]
     res, offs = w.residues, w.offsets
     if args.long_only:
@@ -54,6 +60,8 @@ def main():
         offs = np.zeros(len(keep) + 1, np.int64)
         np.cumsum(lens[keep], out=offs[1:])
     with sw.Database(res, offs) as db:
+        if args.timing:
+            db.set_option(sw.SW_OPT_TIMING, 1)
         out = torch.empty(db.n_seqs, dtype=torch.int32, device="cuda")
         info = []
         for _ in range(args.repeat):
@@ -66,7 +74,11 @@ def main():
                              "intra_cells": st["intra_cells"], "long_items": st["long_items"],
                              "long_overlap": st["long_overlap"], "rows": st["rows"],
                              "waves": st["waves"]})
-    print(json.dumps({"copy_mib": args.copy_mib, "long_only": args.long_only,
+                if args.timing:
+                    info[-1].update({k: round(float(st[k]), 3) for k in
+                                     ("ms_total", "ms_inter", "ms_intra", "ms_rescore")})
+    print(json.dumps({"copy_mib": args.copy_mib, "workload": args.workload,
+                      "long_only": args.long_only,
                       "n_seqs": int(len(offs) - 1), "n_residues": int(offs[-1]),
                       "searches": info}), flush=True)
 
