@@ -320,8 +320,18 @@ enum sw_option {
                              from measured rates; 1..1000 fixes it at that many
                              thousandths of the short bins' cells, with no
                              give-back (for tests and experiments) */
-  SW_OPT_GRAPHS = 7       /* 0/1: replay batched searches from a captured HIP graph
+  SW_OPT_GRAPHS = 7,      /* 0/1: replay batched searches from a captured HIP graph
                              (default 1; graphs are not used while TIMING is on) */
+  SW_OPT_OFFLOAD_BINS = 9  /* single searches (and top-k searches): how many of
+                             the longest short bins (128 sequences each) the
+                             long-pair kernel scores instead of the inter-task
+                             kernel, two sequences per workgroup: -1 (default)
+                             chooses per query, handing over bins while the
+                             longest remaining one would outlast the whole
+                             search on the device (queries long for the
+                             database's size); 0 never; k >= 1 the k longest
+                             (at most all).  Batched, hybrid and
+                             allocation-free searches hand over none */
 };
 int sw_set_option(sw_db* db, int32_t key, int64_t value);
 

@@ -16,13 +16,13 @@ from . import _native
 from ._native import (SwError, SW_ALPHA, SW_BIN_SEQS, SW_PAD_CODE, SW_MIN_BIN_LEN,
                       SW_DEFAULT_LONG_THRESHOLD, SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS,
                       SW_OPT_WAVES, SW_OPT_INTRA_ROWS, SW_OPT_INTRA_WAVES, SW_OPT_GRAPHS,
-                      SW_OPT_HYBRID_SHARE,
+                      SW_OPT_HYBRID_SHARE, SW_OPT_OFFLOAD_BINS,
                       SW_MAX_TOPK, SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL)
 
 __all__ = ["Database", "Context", "SwError", "plan", "pack", "host_search", "SW_ALPHA", "SW_BIN_SEQS", "SW_PAD_CODE",
            "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
            "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS",
-           "SW_OPT_HYBRID_SHARE",
+           "SW_OPT_HYBRID_SHARE", "SW_OPT_OFFLOAD_BINS",
            "SW_MAX_TOPK", "HIT_DTYPE", "SW_MODE_LOCAL", "SW_MODE_GLOBAL", "SW_MODE_SEMIGLOBAL",
            "MODES"]
 

@@ -23,6 +23,7 @@ SW_OPT_TIMING, SW_OPT_SAT_LIMIT, SW_OPT_ROWS, SW_OPT_WAVES, SW_OPT_INTRA_ROWS = 
 SW_OPT_INTRA_WAVES = 6
 SW_OPT_GRAPHS = 7
 SW_OPT_HYBRID_SHARE = 8
+SW_OPT_OFFLOAD_BINS = 9
 SW_MAX_TOPK = 4096
 SW_NOALLOC_SCRATCH_BYTES = 128 << 20
 SW_MODE_LOCAL, SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1, 2

@@ -395,8 +395,9 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
     const uint8_t* __restrict__ sqb = a.res + bb;
     if (a.seg_items) {
       // the segment's window: columns [c0, hi) of both sequences, each cut
-      // to its own length (a is the longer one, so na stays >= 1); an empty
-      // b points at a's residues so that its clamped reads stay in bounds
+      // to its own length (a is the longer one: na = 0 only for two empty
+      // sequences, handled below); an empty b points at a's residues so that
+      // its clamped reads stay in bounds
       const int lo = seg.y * a.seg_cols;
       const int hi = min(na, lo + a.seg_cols);
       const int c0 = max(0, lo - a.seg_overlap);
@@ -405,7 +406,35 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
       sqa += c0;
       sqb = nb > 0 ? sqb + c0 : sqa;
     }
+    // the item's result from its packed maximum b (thread 0): the
+    // segment's maximum, or per half the score or, at the rescoring limit,
+    // an entry of the rescoring list
+    auto emit = [&](uint32_t b) {
+      if (a.seg_best) {
+        a.seg_best[it] = b;
+        return;
+      }
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const int sid = half ? sb : sa;
+        if (sid < 0) continue;
+        const int score = half_score(b, half, a.sat_limit);
+        if (score < 0) {
+          const int idx = atomicAdd(a.flag_count, 1);
+          a.flag_list[idx] = make_int2(sid, bitem.y);
+        } else {
+          a.out[out_off + sid] = score;
+        }
+      }
+    };
     const int n = na > nb ? na : nb;
+    if (n == 0) {
+      // two empty sequences (a pair of a handed-over short bin): maximum 0,
+      // and no residue or boundary-row read; the whole workgroup skips alike
+      if (threadIdx.x == 0) emit(0u);
+      continue;
+    }
+    if (nb == 0) sqb = sqa;   // an empty b reads a's residues (clamped, in bounds)
     const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
     const int T_total = q_last * C2 + kSkew * w_last + C2;
 
@@ -519,27 +548,11 @@ __global__ __launch_bounds__(64 * W2) void k_intra_f16(IntraPairArgs a) {
     for (int off = 32; off > 0; off >>= 1) best = hmax2(best, (uint32_t)__shfl_xor((int)best, off, 64));
     if (lane == 0) lbest[w] = best;
     __syncthreads();
-    if (threadIdx.x == 0 && a.seg_best) {
+    if (threadIdx.x == 0) {
       uint32_t b = lbest[0];
 #pragma unroll
       for (int x = 1; x < W2; ++x) b = hmax2(b, lbest[x]);
-      a.seg_best[it] = b;
-    } else if (threadIdx.x == 0) {
-      uint32_t b = lbest[0];
-#pragma unroll
-      for (int x = 1; x < W2; ++x) b = hmax2(b, lbest[x]);
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const int sid = half ? sb : sa;
-        if (sid < 0) continue;
-        const int score = half_score(b, half, a.sat_limit);
-        if (score < 0) {
-          const int idx = atomicAdd(a.flag_count, 1);
-          a.flag_list[idx] = make_int2(sid, bitem.y);
-        } else {
-          a.out[out_off + sid] = score;
-        }
-      }
+      emit(b);
     }
     __syncthreads();
   }

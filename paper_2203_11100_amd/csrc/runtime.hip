@@ -174,8 +174,13 @@ struct DbData {
   DevBuf<uint8_t> res;              // contiguous residues (original order)
   DevBuf<int64_t> offs;
   DevBuf<int2> d_long_items;        // {sid, 0} for the long list
-  DevBuf<int2> d_long_pairs;        // {sid a, sid b or -1}: the long list in pairs
-  int64_t n_long_pairs = 0;
+  DevBuf<int2> d_long_pairs;        // {sid a, sid b or -1}: the long list in pairs,
+  int64_t n_long_pairs = 0;         // then the short bins' sequences in pairs
+  // the short bins as pairs of neighbouring sequences, bin by bin from the
+  // longest (bin 0), after the long pairs: a long query hands its longest
+  // bins to the long-pair kernel.  bin_pair_end[b] = pairs of bins 0..b,
+  // bin_res_cum[b] = residues of bins 0..b-1
+  std::vector<int64_t> bin_pair_end, bin_res_cum;
   // column segments of the long pairs for short queries: seg_cols columns
   // each, items {pair, segment} pair by pair, pair p's items from
   // d_pair_seg0[p]; any_split when some pair has more than one
@@ -233,6 +238,7 @@ struct Searcher {
   bool use_graphs = true;
   int32_t sat_limit = 32767;
   int32_t opt_rows = 0, opt_waves = 0, opt_intra_rows = 0, opt_intra_waves = 0;
+  int64_t opt_offload = -1;         // short bins for the long-pair kernel: -1 automatic
   // autotuned (rows, waves) per query-length bucket; 0 = not tuned
   int32_t tune_rows[SW_TUNE_BUCKETS] = {}, tune_waves[SW_TUNE_BUCKETS] = {};
   int32_t tune_brows[SW_TUNE_BUCKETS] = {}, tune_bwaves[SW_TUNE_BUCKETS] = {};
@@ -570,7 +576,56 @@ int32_t seg_overlap(const DbData& d, int m, const Matrix& mat, int32_t ge) {
 // and the intra-task profiles' row length.
 struct SearchShape {
   int R, W, m_pad, n_strips, RR, W2, RRr, W2r, m_pad2;
+  int64_t off_bins;   // the longest short bins handed to the long-pair kernel
 };
+
+// Rates of the search kernels on a 256-CU MI355X (cells per second),
+// measured on the benchmark workloads: the inter-task kernel over the
+// device, the long-pair kernel over the device, and one inter-task
+// workgroup (one bin) alone on its CU.
+constexpr double kInterRate = 7.0e12;
+constexpr double kPairRate = 4.5e12;
+constexpr double kBinRate = 3.0e10;
+
+// How many of the longest short bins a query of length m hands to the
+// long-pair kernel (RR query rows per lane).  A bin is 128 sequences on one
+// workgroup, so it takes about m * len * 128 / kBinRate seconds however many
+// CUs are free, while the search's whole work takes about inter cells /
+// kInterRate + long-pair cells / kPairRate on the device (the pair rate
+// scaled by the query rows' share of the passes' rows).  For a long query
+// against few short sequences the longest bin outlasts that (the critical
+// path of the inter-task kernel); in the long-pair kernel its sequences go
+// two per workgroup and spread over the CUs.  Bins are handed over, longest
+// first, while the longest remaining one would outlast the whole work.
+int64_t pick_offload(const Searcher* db, int m, int RR) {
+  const DbData& D = *db->d;
+  const int64_t nb = D.plan.n_bins;
+  if (db->opt_offload >= 0) return std::min<int64_t>(db->opt_offload, nb);
+  if (nb == 0 || m <= 0 || RR <= 0 || D.bin_res_cum.size() != (size_t)nb + 1) return 0;
+  const double cus = std::max(D.n_cus, 1) / 256.0;
+  const int64_t pass_rows = 64 * (int64_t)RR;
+  const double row_share = (double)m / (double)((m + pass_rows - 1) / pass_rows * pass_rows);
+  const double inter_rate = kInterRate * cus, pair_rate = kPairRate * cus * row_share;
+  double inter = (double)m * (double)(D.n_res - D.long_residues);
+  double pair = (double)m * (double)D.long_residues;
+  int64_t k = 0;
+  while (k < nb) {
+    const double t_bin = (double)m * (double)D.plan.bins[(size_t)k * 4 + 2] * SW_BIN_SEQS / kBinRate;
+    if (t_bin <= inter / inter_rate + pair / pair_rate) break;
+    const double moved = (double)m * (double)(D.bin_res_cum[(size_t)k + 1] - D.bin_res_cum[(size_t)k]);
+    inter -= moved;
+    pair += moved;
+    ++k;
+  }
+  return k;
+}
+
+// Boundary-row length one workgroup of the long-pair kernel needs for whole
+// sequences: the longest long sequence, or the longest short one when short
+// bins are handed over.
+int64_t pair_stride(const DbData& d) {
+  return std::max<int64_t>({(int64_t)d.plan.max_long_len, (int64_t)d.plan.max_short_len, 1});
+}
 
 SearchShape search_shape(const Searcher* db, int m) {
   SearchShape sh{};
@@ -587,6 +642,7 @@ SearchShape search_shape(const Searcher* db, int m) {
   // the intra-task profiles serve every intra-task launch of the query (long
   // list, rescoring, hit ends): pad to the largest pass, 64 x 8 rows
   sh.m_pad2 = intra_rows_pad(m);
+  sh.off_bins = pick_offload(db, m, sh.RR);
   return sh;
 }
 
@@ -637,24 +693,29 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
 int reserve_search_scratch(Searcher* db, const SearchShape& sh, SearchScratch* X) {
   hipError_t e;
   const int64_t n_long = db->d->plan.n_long;
+  const int64_t off_pairs = sh.off_bins > 0 ? db->d->bin_pair_end[(size_t)sh.off_bins - 1] : 0;
+  const bool pairs = n_long > 0 || off_pairs > 0;
   if ((e = db->prof.reserve((size_t)sh.n_strips * prof_strip_dwords(sh.R))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
   if ((e = db->prof2.reserve((size_t)kIntraCodes * sh.m_pad2)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
-  if (n_long > 0 && (e = db->prof3.reserve((size_t)kIntraCodes * (sh.m_pad2 / 2))) != hipSuccess)
+  if (pairs && (e = db->prof3.reserve((size_t)kIntraCodes * (sh.m_pad2 / 2))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("profile allocation: ") + hipGetErrorString(e));
-  const int grid_long = (int)std::min<int64_t>(db->d->n_long_pairs, kIntraGridLong);
-  const int grid_seg = (int)std::min<int64_t>(db->d->n_seg_items, kIntraGridLong);
-  if (n_long > 0 && (e = db->rb_long.reserve(std::max<size_t>(
-                         {(size_t)std::max(grid_long, 1) * (size_t)std::max<int32_t>(
-                                                               db->d->plan.max_long_len, 1),
-                          (size_t)grid_seg * (size_t)seg_stride(*db->d), 1}))) != hipSuccess)
+  const int grid_long =
+      (int)std::min<int64_t>(db->d->n_long_pairs + off_pairs, kIntraGridLong);
+  const int grid_seg = (int)std::min<int64_t>(db->d->n_seg_items + off_pairs, kIntraGridLong);
+  if (n_long > 0 && off_pairs > 0 &&
+      (e = db->seg_best.reserve((size_t)(db->d->n_seg_items + off_pairs))) != hipSuccess)
+    return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
+  if (pairs && (e = db->rb_long.reserve(std::max<size_t>(
+                    {(size_t)std::max(grid_long, 1) * (size_t)pair_stride(*db->d),
+                     (size_t)grid_seg * (size_t)seg_stride(*db->d), 1}))) != hipSuccess)
     return fail(SW_ENOMEM, std::string("long scratch: ") + hipGetErrorString(e));
   X->rb = db->rb.p;
   X->flags = db->flags.p;
   X->prof = db->prof.p;
   X->prof2 = db->prof2.p;
-  X->prof3 = n_long > 0 ? db->prof3.p : nullptr;
+  X->prof3 = pairs ? db->prof3.p : nullptr;
   X->rb_long = db->rb_long.p;
   X->grid_long = grid_long;
   X->grid_seg = grid_seg;
@@ -688,15 +749,23 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
   const int R = sh.R, W = sh.W, RR = sh.RR, W2 = sh.W2, RRr = sh.RRr, W2r = sh.W2r;
   const int m_pad2 = sh.m_pad2;
   const int64_t n_long = db->d->plan.n_long;
+  const int n_bins = (int)db->d->plan.n_bins;
   int2* const flist = reinterpret_cast<int2*>(X.flags + 2);
+  // short queries: the long pairs in column segments (seg_overlap), each
+  // handed-over pair one segment; the longest short bins go to the pair
+  // kernel as pairs (pick_offload; the bin runners' searches hand none over)
+  const int32_t overlap = n_long > 0 ? seg_overlap(*db->d, m, mat, ge) : -1;
+  const bool segmented = overlap >= 0 && X.seg_best && X.grid_seg > 0;
+  const int off_bins = (int)std::min<int64_t>(std::max<int64_t>(sh.off_bins, 0), n_bins);
+  const int64_t off_pairs = off_bins > 0 ? db->d->bin_pair_end[(size_t)off_bins - 1] : 0;
+  const bool pairs = n_long > 0 || off_pairs > 0;
 
   const int t_total = time_begin(db, kTimeTotal, s);
   if ((e = launch_profile(d_query, m, mat, X.prof, sh.m_pad, R, X.prof2,
-                          n_long > 0 ? X.prof3 : nullptr, m_pad2, X.flags, s)) != hipSuccess)
+                          pairs ? X.prof3 : nullptr, m_pad2, X.flags, s)) != hipSuccess)
     return hip_fail(e, "profile kernel");
+  if (pairs && (e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
 
-  // long sequences: packed intra-task kernel on the auxiliary stream,
-  // overlapped with the inter-task bins
   IntraArgs ia{};
   ia.res = db->d->res.p;
   ia.offs = db->d->offs.p;
@@ -708,15 +777,45 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
   ia.go = go;
   ia.ge = ge;
   ia.out = d_out;
-  if (n_long > 0) {
-    if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess) return hip_fail(e, "event");
+
+  // short sequences: inter-task kernel over the bins not handed over
+  auto run_bins = [&]() -> int {
+    InterArgs a{};
+    a.res2 = reinterpret_cast<const uint2*>(db->d->packed.p);
+    a.bins = db->d->bins.p;
+    a.bin_begin = off_bins;
+    a.n_strips = sh.n_strips;
+    a.prof = X.prof;
+    a.go2 = half_pair(go);
+    a.ge2 = half_pair(ge);
+    a.rb = X.rb;
+    a.slot_seq = db->d->slot_seq.p;
+    a.out = d_out;
+    a.flag_count = X.flags;
+    a.flag_list = flist;
+    a.sat_limit = effective_limit(db->sat_limit);
+    if (bins) return (*bins)(a, R, W, s);
+    if (n_bins > off_bins) {
+      const int ti = time_begin(db, kTimeInter, s);
+      if ((e = launch_inter(R, W, n_bins - off_bins, a, s)) != hipSuccess)
+        return hip_fail(e, "inter-task kernel");
+      time_end(db, ti, s);
+      ++db->stats.n_inter_launches;
+    }
+    return SW_OK;
+  };
+
+  // long sequences (and handed-over bins): packed long-pair kernel on the
+  // auxiliary stream, overlapped with the inter-task bins
+  auto run_pairs = [&]() -> int {
+    if (!pairs) return SW_OK;
     if ((e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
       return hip_fail(e, "stream wait");
     IntraPairArgs la{};
     la.res = db->d->res.p;
     la.offs = db->d->offs.p;
     la.items = db->d->d_long_pairs.p;
-    la.count = (int32_t)db->d->n_long_pairs;
+    la.count = (int32_t)(db->d->n_long_pairs + off_pairs);
     la.prof3 = X.prof3;
     la.m_pad2 = m_pad2;
     la.n_pass = (m + 64 * RR - 1) / (64 * RR);
@@ -724,22 +823,19 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
     la.ge2 = half_pair(ge);
     la.sat_limit = effective_limit(db->sat_limit);
     la.scratch = X.rb_long;
-    la.scratch_stride = std::max<int64_t>(db->d->plan.max_long_len, 1);
+    la.scratch_stride = pair_stride(*db->d);
     la.out = d_out;
     la.flag_count = X.flags;
     la.flag_list = flist;
-    int grid = X.grid_long;
-    // short queries: the long pairs in column segments (seg_overlap)
-    const int32_t overlap = seg_overlap(*db->d, m, mat, ge);
-    const bool segmented = overlap >= 0 && X.seg_best && X.grid_seg > 0;
+    int grid = std::min<int>(X.grid_long, la.count);
     if (segmented) {
       la.seg_items = db->d->d_seg_items.p;
-      la.count = (int32_t)db->d->n_seg_items;
+      la.count = (int32_t)(db->d->n_seg_items + off_pairs);
       la.seg_cols = db->d->seg_cols;
       la.seg_overlap = overlap;
       la.seg_best = X.seg_best;
       la.scratch_stride = seg_stride(*db->d);
-      grid = X.grid_seg;
+      grid = std::min<int>(X.grid_seg, la.count);
     }
     const int tl = time_begin(db, kTimeIntra, db->aux_stream);
     if ((e = launch_intra_pairs(RR, W2, grid, la, db->aux_stream)) != hipSuccess)
@@ -748,41 +844,28 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
     db->stats.long_overlap = segmented ? overlap : -1;
     if (segmented &&
         (e = launch_long_combine(db->d->d_long_pairs.p, db->d->d_pair_seg0.p,
-                                 (int32_t)db->d->n_long_pairs, X.seg_best, la.sat_limit, d_out,
-                                 X.flags, flist, db->aux_stream)) != hipSuccess)
+                                 (int32_t)(db->d->n_long_pairs + off_pairs), X.seg_best,
+                                 la.sat_limit, d_out, X.flags, flist, db->aux_stream)) !=
+            hipSuccess)
       return hip_fail(e, "segment maxima");
     time_end(db, tl, db->aux_stream);
     if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "event");
-  }
+    return SW_OK;
+  };
 
-  // short sequences: inter-task kernel over all bins
-  InterArgs a{};
-  a.res2 = reinterpret_cast<const uint2*>(db->d->packed.p);
-  a.bins = db->d->bins.p;
-  a.bin_begin = 0;
-  a.n_strips = sh.n_strips;
-  a.prof = X.prof;
-  a.go2 = half_pair(go);
-  a.ge2 = half_pair(ge);
-  a.rb = X.rb;
-  a.slot_seq = db->d->slot_seq.p;
-  a.out = d_out;
-  a.flag_count = X.flags;
-  a.flag_list = flist;
-  a.sat_limit = effective_limit(db->sat_limit);
-  const int n_bins = (int)db->d->plan.n_bins;
+  // The bins go first: the longest bin's workgroup is the inter-task
+  // kernel's critical path and starts at once, before the long pairs' large
+  // workgroups fill the CUs.  A bin runner (hybrid and allocation-free
+  // searches) returns only when its bins are done, so there the pairs go first.
+  int rc;
   if (bins) {
-    const int rc = (*bins)(a, R, W, s);
-    if (rc != SW_OK) return rc;
-  } else if (n_bins > 0) {
-    const int ti = time_begin(db, kTimeInter, s);
-    if ((e = launch_inter(R, W, n_bins, a, s)) != hipSuccess) return hip_fail(e, "inter-task kernel");
-    time_end(db, ti, s);
-    ++db->stats.n_inter_launches;
+    if ((rc = run_pairs()) != SW_OK || (rc = run_bins()) != SW_OK) return rc;
+  } else {
+    if ((rc = run_bins()) != SW_OK || (rc = run_pairs()) != SW_OK) return rc;
   }
   // both packed kernels fill the rescoring list: join before consuming it
-  if (n_long > 0 && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
+  if (pairs && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
     return hip_fail(e, "stream wait");
   {
     // exact rescoring of sequences whose half-precision score reached the
@@ -803,9 +886,10 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
 
   db->stats.rows = R;
   db->stats.waves = W;
-  const int64_t long_res = db->d->long_residues;
-  db->stats.inter_cells += (int64_t)m * (db->d->n_res - long_res);
-  db->stats.intra_cells += (int64_t)m * long_res;
+  const int64_t pair_res =
+      db->d->long_residues + (off_bins > 0 ? db->d->bin_res_cum[(size_t)off_bins] : 0);
+  db->stats.inter_cells += (int64_t)m * (db->d->n_res - pair_res);
+  db->stats.intra_cells += (int64_t)m * pair_res;
   return SW_OK;
 }
 
@@ -1480,6 +1564,30 @@ int sw_db_load_ex(const uint8_t* residues, const int64_t* offsets, int64_t n_seq
   }
   h_pair_seg0[h_long_pairs.size()] = (int32_t)h_seg_items.size();
   d->n_seg_items = (int64_t)h_seg_items.size();
+  // then the short bins' sequences in pairs of neighbours, bin by bin, each
+  // pair also one whole-sequence segment item (for short queries, whose long
+  // pairs run in segments)
+  try {
+    d->bin_pair_end.resize((size_t)P.n_bins);
+    d->bin_res_cum.assign((size_t)P.n_bins + 1, 0);
+    for (int64_t b = 0; b < P.n_bins; ++b) {
+      const int32_t c = P.bin_count[(size_t)b];
+      const int32_t* slot = &h_slots[(size_t)b * SW_BIN_SEQS];
+      int64_t res_b = 0;
+      for (int32_t t = 0; t < c; t += 2) {
+        h_seg_items.push_back(make_int2((int)h_long_pairs.size(), 0));
+        h_pair_seg0.push_back((int32_t)h_seg_items.size());
+        h_long_pairs.push_back(make_int2(slot[t], t + 1 < c ? slot[t + 1] : -1));
+        res_b += offsets[slot[t] + 1] - offsets[slot[t]];
+        if (t + 1 < c) res_b += offsets[slot[t + 1] + 1] - offsets[slot[t + 1]];
+      }
+      d->bin_pair_end[(size_t)b] = (int64_t)h_long_pairs.size() - d->n_long_pairs;
+      d->bin_res_cum[(size_t)b + 1] = d->bin_res_cum[(size_t)b] + res_b;
+    }
+  } catch (...) {
+    destroy_db(h);
+    return fail(SW_ENOMEM, "host staging allocation failed");
+  }
 
   auto alloc_fail = [&](hipError_t err, const char* what) {
     destroy_db(h);
@@ -1751,7 +1859,10 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   if ((e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
       hipSuccess)
     return hip_fail(e, "query upload");
-  const SearchShape sh = search_shape(db, query_len);
+  // every short bin takes part in the split (none handed to the long-pair
+  // kernel): the host takes sequences from the back of the same order
+  SearchShape sh = search_shape(db, query_len);
+  sh.off_bins = 0;
   SearchScratch X;
   if ((rc = reserve_search_scratch(db, sh, &X)) != SW_OK) return rc;
 
@@ -2009,7 +2120,10 @@ static int impl_search_async_noalloc(swdb::Searcher* db, const uint8_t* d_query,
     set_error("");
     return SW_OK;
   }
-  const SearchShape sh = search_shape(db, query_len);
+  // no bins handed to the long-pair kernel: its boundary rows here are
+  // sized for the long list only
+  SearchShape sh = search_shape(db, query_len);
+  sh.off_bins = 0;
   NoAllocLayout L;
   if ((rc = noalloc_layout(db, sh, base, &L)) != SW_OK) return rc;
   // the short bins in chunks whose boundary rows fit the 96 MiB part; each
@@ -2168,6 +2282,11 @@ static int impl_set_option(swdb::Searcher* db, int32_t key, int64_t value) {
       if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8)
         return fail(SW_EINVAL, "intra waves must be 0, 1, 2, 4 or 8");
       db->opt_intra_waves = (int32_t)value;
+      return SW_OK;
+    case SW_OPT_OFFLOAD_BINS:
+      if (value < -1 || value > INT32_MAX)
+        return fail(SW_EINVAL, "offloaded bins must be -1 (automatic) or 0..2^31-1");
+      db->opt_offload = value;
       return SW_OK;
     default:
       return fail(SW_EINVAL, "unknown option " + std::to_string(key));
@@ -2384,8 +2503,10 @@ static int impl_autotune(swdb::Searcher* db, const int32_t* query_lens, int32_t 
   const bool saved_timing = db->timing, saved_graphs = db->use_graphs;
   const int32_t saved_r = db->opt_rows, saved_w = db->opt_waves;
   const int32_t saved_ir = db->opt_intra_rows, saved_iw = db->opt_intra_waves;
+  const int64_t saved_off = db->opt_offload;
   db->timing = true;
   db->use_graphs = false;
+  db->opt_offload = 0;   // the inter-task forms are measured over every bin
   int rc = SW_OK;
   // untuned while measuring, so the fitted candidate (0, 0) is what it says
   for (int b = 0; b < SW_TUNE_BUCKETS; ++b)
@@ -2456,6 +2577,7 @@ static int impl_autotune(swdb::Searcher* db, const int32_t* query_lens, int32_t 
   db->opt_waves = saved_w;
   db->opt_intra_rows = saved_ir;
   db->opt_intra_waves = saved_iw;
+  db->opt_offload = saved_off;
   db->stats = sw_stats{};
   if (rc != SW_OK) return rc;
   // (0, 0) chosen means "fitted": stored as untuned so the fit stays per query
@@ -2630,6 +2752,7 @@ int sw_ctx_create(sw_db* h, sw_ctx** out_ctx) {
     c->s.opt_waves = h->main.opt_waves;
     c->s.opt_intra_rows = h->main.opt_intra_rows;
     c->s.opt_intra_waves = h->main.opt_intra_waves;
+    c->s.opt_offload = h->main.opt_offload;
     for (int b = 0; b < SW_TUNE_BUCKETS; ++b) {
       c->s.tune_rows[b] = h->main.tune_rows[b];
       c->s.tune_waves[b] = h->main.tune_waves[b];

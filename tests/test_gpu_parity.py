@@ -43,21 +43,27 @@ def _ragged_db(seed=0):
     return swinputs.make_database(lengths, rng)
 
 
-def test_plain_small_workload(sw):
+@pytest.mark.parametrize("off", [-1, 0])
+def test_plain_small_workload(sw, off):
     w = swinputs.config("plain-small")
-    say("plain-small: 2000 seqs, m=144")
+    say("plain-small: 2000 seqs, m=144, offload %d" % off)
     with sw.Database(w.residues, w.offsets) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
         got = db.search(w.queries[0], w.matrix, 10, 2)
     want = _oracle(w.queries[0], w.residues, w.offsets)
     assert (got == want).all(), np.nonzero(got != want)[0][:10]
 
 
+@pytest.mark.parametrize("off", [0, -1])
 @pytest.mark.parametrize("m", [1, 2, 15, 16, 17, 31, 32, 33, 100, 255, 257, 600])
-def test_ragged_database_query_lengths(sw, m):
+def test_ragged_database_query_lengths(sw, m, off):
+    """Every bin in the inter-task kernel (off = 0), or the longest ones
+    handed to the long-pair kernel as the search decides (off = -1)."""
     res, offs = _ragged_db()
     q = swinputs.random_residues(m, np.random.default_rng(m))
-    say("ragged db, m=%d" % m)
+    say("ragged db, m=%d, offload %d" % (m, off))
     with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
         got = db.search(q, B62, 10, 2)
     assert (got == _oracle(q, res, offs)).all()
 
@@ -71,6 +77,7 @@ def test_strip_and_wave_options(sw, rows, waves):
     q = swinputs.random_residues(333, np.random.default_rng(5))
     say("rows=%d waves=%d" % (rows, waves))
     with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, 0)     # every bin in the inter-task kernel
         db.set_option(sw.SW_OPT_ROWS, rows)
         db.set_option(sw.SW_OPT_WAVES, waves)
         got = db.search(q, B62, 10, 2)
@@ -80,23 +87,26 @@ def test_strip_and_wave_options(sw, rows, waves):
 
 
 def test_consecutive_searches_change_schedule(sw):
-    """Searches in a row on one database, each with another schedule and
-    query length (one strip, several rounds, a single-wave form, an empty
-    query): the first strip of every search reads the boundary rows the
-    previous search left, which must be zeros whatever its schedule."""
+    """Searches in a row on one database, each with another schedule, query
+    length (one strip, several rounds, a single-wave form, an empty query)
+    and number of bins handed to the long-pair kernel: the first strip of
+    every search reads the boundary rows the previous search left, which
+    must be zeros whatever its schedule and whichever bins it skipped."""
     res, offs = _ragged_db(7)
     rng = np.random.default_rng(70)
-    plan = [(333, 0, 0), (5, 12, 16), (700, 20, 12), (0, 0, 0), (40, 14, 16),
-            (150, 16, 1), (1, 0, 0), (900, 32, 8), (211, 18, 12), (333, 0, 0)]
+    plan = [(333, 0, 0, 0), (5, 12, 16, 3), (700, 20, 12, -1), (0, 0, 0, 0), (40, 14, 16, 1),
+            (150, 16, 1, 0), (1, 0, 0, 5), (900, 32, 8, 2), (211, 18, 12, 0), (333, 0, 0, -1),
+            (333, 0, 0, 0)]
     say("consecutive searches, %d schedules" % len(plan))
     with sw.Database(res, offs) as db:
-        for m, rows, waves in plan:
+        for m, rows, waves, off in plan:
             q = swinputs.random_residues(m, rng)
             db.set_option(sw.SW_OPT_ROWS, rows)
             db.set_option(sw.SW_OPT_WAVES, waves)
+            db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
             got = db.search(q, B62, 10, 2)
             want = _oracle(q, res, offs) if m else np.zeros(len(offs) - 1, np.int32)
-            assert (got == want).all(), (m, rows, waves)
+            assert (got == want).all(), (m, rows, waves, off)
 
 
 # (rows, waves, efficiency per strip slot) of the library's fitted schedules
@@ -124,6 +134,7 @@ def test_fitted_schedule(sw, m):
     q = swinputs.random_residues(m, np.random.default_rng(41))
     say("fitted schedule m=%d" % m)
     with sw.Database(res, offs) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, 0)     # every bin in the inter-task kernel
         got = db.search(q, B62, 10, 2)
         st = db.stats()
     assert (st["rows"], st["waves"]) == _fit_schedule(m)
@@ -180,6 +191,7 @@ def test_long_pairs_in_column_segments(sw, m, go, ge, segmented):
     say("segments: m=%d gaps %d/%d reach %s" % (m, go, ge, reach))
     want = _oracle(q, res, offs, go=go, ge=ge)
     with sw.Database(res, offs, long_threshold=500) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, 0)     # the long pairs alone in the pair kernel
         for limit in (32767, 40):
             db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
             got = db.search(q, B62, go, ge)
@@ -189,6 +201,90 @@ def test_long_pairs_in_column_segments(sw, m, go, ge, segmented):
             n_pairs = (db.info()["n_long"] + 1) // 2
             assert (st["long_items"] > n_pairs) if segmented else (st["long_items"] == n_pairs)
     assert want[big] == sum(int(B62[c, c]) for c in q)
+
+
+def _bins_db(seed, with_long):
+    """Short sequences of every length class (empty ones, a last bin with an
+    odd count) and, optionally, a few long ones."""
+    rng = np.random.default_rng(seed)
+    parts = [[0, 0, 0, 1, 2, 3], rng.integers(1, 60, 200), rng.integers(60, 1200, 500),
+             [1999, 2000, 2047]]
+    if with_long:
+        parts.append([2048, 2600, 4100])
+    lengths = np.concatenate(parts).astype(np.int64)
+    rng.shuffle(lengths)
+    return swinputs.make_database(lengths, rng)
+
+
+def _bin_pairs(lens, k, t_long):
+    """Pairs of neighbouring sequences in the k longest short bins."""
+    short = np.sort(lens[lens < t_long])[::-1]
+    counts = [min(128, len(short) - 128 * b) for b in range((len(short) + 127) // 128)]
+    return sum((c + 1) // 2 for c in counts[:k])
+
+
+@pytest.mark.parametrize("with_long", [True, False])
+@pytest.mark.parametrize("off", [0, 1, 2, 6, 1000, -1])
+def test_short_bins_through_the_pair_kernel(sw, with_long, off):
+    """The longest short bins handed to the long-pair kernel (two sequences
+    per workgroup; an odd bin leaves one alone, two empty sequences score 0
+    without reading anything): every score exact, with and without long
+    sequences, for a long query (whole pairs) and a short one (the long
+    pairs in column segments, each handed-over pair one segment), and with
+    the rescoring limit forced low so that the pair kernel's flags reach
+    the 32-bit rescoring."""
+    res, offs = _bins_db(31, with_long)
+    lens = np.diff(offs)
+    rng = np.random.default_rng(32)
+    t_long = sw.SW_DEFAULT_LONG_THRESHOLD
+    # a copy of the long query inside one sequence of the longest bin: a
+    # score above the half-precision range
+    q = swinputs.random_residues(1300, rng)
+    top = int(np.nonzero(lens == 2047)[0][0])
+    res = res.copy()
+    res[offs[top] + 300:offs[top] + 1600] = q
+    for m, qq in ((1300, q), (90, swinputs.random_residues(90, rng))):
+        want = _oracle(qq, res, offs)
+        with sw.Database(res, offs) as db:
+            db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
+            n_long_pairs = (db.info()["n_long"] + 1) // 2
+            for limit in (32767, 40):
+                say("offload %d, long %s, m=%d, limit %d" % (off, with_long, m, limit))
+                db.set_option(sw.SW_OPT_SAT_LIMIT, limit)
+                got = db.search(qq, B62, 10, 2)
+                st = db.stats()
+                assert (got == want).all(), np.nonzero(got != want)[0][:10]
+                if limit == 40:
+                    assert st["n_rescored"] == int((want >= 40).sum())
+                segmented = st["long_items"] > 0 and st["long_overlap"] >= 0
+                if off >= 0 and not segmented:
+                    assert st["long_items"] == n_long_pairs + _bin_pairs(lens, off, t_long)
+                if off == -1 and m == 1300:
+                    assert st["long_items"] > n_long_pairs    # the search hands some over
+
+
+def test_offload_decision_follows_the_database_shape(sw):
+    """The automatic choice: a database of many sequences of similar length
+    keeps every bin in the inter-task kernel; a long query against a few
+    hundred short sequences hands bins over (its longest bin would otherwise
+    outlast the rest of the search); both exact on sampled sequences."""
+    rng = np.random.default_rng(33)
+    res, offs = swinputs.make_database(rng.integers(200, 301, 60_000).astype(np.int64), rng)
+    q = swinputs.random_residues(400, rng)
+    ids = rng.choice(len(offs) - 1, 200, replace=False)
+    with sw.Database(res, offs) as db:
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+    assert st["long_items"] == 0
+    assert (got[ids] == _oracle(q, res, offs, ids=ids)).all()
+    res, offs = swinputs.make_database(
+        swinputs.lognormal_lengths(700, 355.0, 0.75, 20, 2000, rng), rng)
+    q = swinputs.random_residues(3000, rng)
+    with sw.Database(res, offs) as db:
+        got = db.search(q, B62, 10, 2)
+        st = db.stats()
+    assert st["long_items"] > 0
+    assert (got == _oracle(q, res, offs)).all()
 
 
 @pytest.mark.parametrize("limit", [0, 40, 32767])
@@ -215,10 +311,12 @@ def test_forced_rescoring(sw, limit):
         assert st["n_rescored"] == int((want >= 2048).sum())
 
 
-def test_scores_around_the_half_precision_limit(sw):
+@pytest.mark.parametrize("off", [0, -1])
+def test_scores_around_the_half_precision_limit(sw, off):
     """Planted matches scoring ~1,400..2,500 in the packed kernels' bins:
     every score exact, and exactly those >= 2048 rescored in 32 bits (single
-    and batched searches)."""
+    and batched searches; the single search with every bin in the
+    inter-task kernel, or the longest handed to the long-pair kernel)."""
     rng = np.random.default_rng(31)
     W = swinputs.ALPHABET.index("W")
     C = swinputs.ALPHABET.index("C")
@@ -241,8 +339,9 @@ def test_scores_around_the_half_precision_limit(sw):
     # all in bins; then the planted ones (>= 257 residues) in the long list,
     # scored by the packed intra-task kernel (batched: long bins)
     for t_long in (10**6, 250):
-        say("half-precision limit, long threshold %d" % t_long)
+        say("half-precision limit, long threshold %d, offload %d" % (t_long, off))
         with sw.Database(res, offs, long_threshold=t_long) as db:
+            db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
             if t_long == 250:
                 assert db.info()["n_long"] >= 9
             got = db.search(q, B62, 10, 2)
@@ -256,8 +355,10 @@ def test_scores_around_the_half_precision_limit(sw):
         assert stb["n_rescored"] == sum(int((wq >= 2048).sum()) for wq in wants)
 
 
-def test_planted_overflow_in_short_bins(sw):
-    """Scores above 32767 inside the 16-bit kernel's bins are rescored exactly."""
+@pytest.mark.parametrize("off", [0, -1])
+def test_planted_overflow_in_short_bins(sw, off):
+    """Scores above 32767 inside the packed kernels' bins are rescored
+    exactly (every bin in the inter-task kernel, or as the search decides)."""
     rng = np.random.default_rng(8)
     W = swinputs.ALPHABET.index("W")
     q = np.concatenate([np.full(2700, W, np.uint8), swinputs.random_residues(1200, rng)])
@@ -273,8 +374,9 @@ def test_planted_overflow_in_short_bins(sw):
     res = np.concatenate(seqs)
     diag = int(sum(int(B62[c, c]) for c in q))
     assert diag > 32767
-    say("planted overflow")
+    say("planted overflow, offload %d" % off)
     with sw.Database(res, offs, long_threshold=10**6) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
         got = db.search(q, B62, 10, 2)
         st = db.stats()
     assert st["n_rescored"] >= len(planted)
@@ -283,15 +385,17 @@ def test_planted_overflow_in_short_bins(sw):
     assert (got == _oracle(q, res, offs)).all()
 
 
+@pytest.mark.parametrize("off", [0, 4])
 @pytest.mark.parametrize("gaps", [(0, 0), (5, 5), (11, 1), (40, 1), (1000, 1000), (12, 2),
                                   (3000, 2500), (5000, 1)])
-def test_gap_penalties(sw, gaps):
+def test_gap_penalties(sw, gaps, off):
     """Gap penalties from none to above the binary16 exact range (passed to
-    the packed kernels as 2048)."""
+    the packed kernels as 2048), with the four longest bins in either kernel."""
     res, offs = _ragged_db(4)
     q = swinputs.random_residues(180, np.random.default_rng(9))
-    say("gaps", gaps)
+    say("gaps", gaps, "offload", off)
     with sw.Database(res, offs, long_threshold=1000) as db:
+        db.set_option(sw.SW_OPT_OFFLOAD_BINS, off)
         got = db.search(q, B62, *gaps)
     assert (got == _oracle(q, res, offs, B62, *gaps)).all()
 
