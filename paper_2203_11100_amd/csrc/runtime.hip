@@ -595,8 +595,15 @@ constexpr double kBinRate = 3.0e10;
 // scaled by the query rows' share of the passes' rows).  For a long query
 // against few short sequences the longest bin outlasts that (the critical
 // path of the inter-task kernel); in the long-pair kernel its sequences go
-// two per workgroup and spread over the CUs.  Bins are handed over, longest
-// first, while the longest remaining one would outlast the whole work.
+// two per workgroup and spread over the CUs.  When the longest bin would
+// outlast the whole work, bins are handed over, longest first, until the
+// longest remaining one ends within kOffloadMargin of it (the bin's own rate
+// drops with the device's clock under full load, and the pair kernel takes
+// the handed-over work beside its own).  Measured on the long-sequence mix,
+// 6..16 bins hand over give the same time within 1 % (7 chosen), 8 % below
+// none; on the plain workload, whose longest bin ends within the search's
+// work, handing any over only adds time (2 bins +0.4 %, 40 bins +7 %).
+constexpr double kOffloadMargin = 0.7;
 int64_t pick_offload(const Searcher* db, int m, int RR) {
   const DbData& D = *db->d;
   const int64_t nb = D.plan.n_bins;
@@ -611,7 +618,7 @@ int64_t pick_offload(const Searcher* db, int m, int RR) {
   int64_t k = 0;
   while (k < nb) {
     const double t_bin = (double)m * (double)D.plan.bins[(size_t)k * 4 + 2] * SW_BIN_SEQS / kBinRate;
-    if (t_bin <= inter / inter_rate + pair / pair_rate) break;
+    if (t_bin <= (k > 0 ? kOffloadMargin : 1.0) * (inter / inter_rate + pair / pair_rate)) break;
     const double moved = (double)m * (double)(D.bin_res_cum[(size_t)k + 1] - D.bin_res_cum[(size_t)k]);
     inter -= moved;
     pair += moved;
