@@ -4,8 +4,9 @@ Runs, in one process:
   1. a plain device-to-device copy of COPY_MIB MiB (torch), the calibration
      kernel of known traffic: COPY_MIB MiB read and COPY_MIB MiB written;
   2. a benchmark workload's searches for the chosen queries (default: all;
-     --workload plain, the 20-query plain workload, or long-mix, its 10
-     queries against the long-sequence mix), with the database already
+     --workload plain, the 20-query plain workload, long-mix, its 10
+     queries against the long-sequence mix, or plain-small, one 144-residue
+     query against 2,000 sequences), with the database already
      resident; with --long-only, the plain queries against a database of only
      the plain database's long sequences (2,048 residues or more), so the
      long-sequence kernel runs alone.  --timing adds each search's kernel
@@ -15,7 +16,7 @@ Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
 block per run) each dispatch gets its counter value; dividing a search
 kernel's value by the copy kernel's value per MiB converts it into bytes.
 
-    python pmc.py [--workload plain|long-mix] [--queries 0,19] [--copy-mib 1024]
+    python pmc.py [--workload plain|long-mix|plain-small] [--queries 0,19] [--copy-mib 1024]
                   [--long-only] [--repeat N] [--timing]
 """
 import argparse
@@ -36,7 +37,7 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=COPY_MIB)
     ap.add_argument("--long-only", action="store_true")
     ap.add_argument("--repeat", type=int, default=1)
-    ap.add_argument("--workload", default="plain", choices=("plain", "long-mix"))
+    ap.add_argument("--workload", default="plain", choices=("plain", "long-mix", "plain-small"))
     ap.add_argument("--timing", action="store_true")
     args = ap.parse_args()
     import numpy as np
