@@ -126,6 +126,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libswdb.so is not built (%s); run "
                               "`python -m paper_2203_11100_amd.build`" % LIB_PATH)
+        try:
+            import torch
+            # PyTorch ships its own HIP runtime; it must open the GPU before
+            # this library's runtime does, or it finds no device afterwards
+            torch.cuda.is_available()
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

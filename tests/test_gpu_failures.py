@@ -82,3 +82,27 @@ def test_device_memory_exhausted_is_enomem(sw):
         ids = rng.choice(db.n_seqs, 50, replace=False)
         got = db.search(q, B62, 10, 2)
         assert (got[ids] == ocpu.search(q, res, offs, B62, 10, 2, ids=ids)).all()
+
+
+def test_library_first_then_torch_in_a_fresh_process():
+    """A process that loads a database before it touches PyTorch's GPU
+    functions can still use them: the binding lets PyTorch's HIP runtime
+    open the device first."""
+    import subprocess
+    import os
+    code = ("import numpy as np, swinputs, paper_2203_11100_amd as sw\n"
+            "rng = np.random.default_rng(0)\n"
+            "res, offs = swinputs.make_database(rng.integers(20, 300, 500).astype(np.int64), rng)\n"
+            "db = sw.Database(res, offs)\n"
+            "got = db.search(swinputs.random_residues(50, rng), swinputs.blosum62(), 10, 2)\n"
+            "import torch\n"
+            "s = torch.cuda.Stream()\n"
+            "x = torch.ones(4, device='cuda') * 2\n"
+            "assert float(x.sum()) == 8.0 and got.shape == (500,)\n"
+            "db.close()\n"
+            "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    say("database first, then torch, in a child process")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
