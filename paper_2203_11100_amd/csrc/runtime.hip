@@ -1259,14 +1259,18 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
   ia.go = B.go;
   ia.ge = B.ge;
   ia.out = B.d_out;
-  // Very long sequences first, on the same stream: the persistent batched
-  // kernel holds every CU until its list is drained, so a concurrent launch
-  // would only get CUs at the end.  These items are few and run in parallel.
-  // The very long sequences go in pairs through the packed long-pair
-  // kernel (binary16, two sequences per lane), each item with its query's
-  // profile and score row; sequences at the rescoring limit join the list
-  // the batched kernel fills.
-  if (B.n_long_items > 0) {
+  // Very long sequences: the packed long-pair kernel (binary16, two
+  // sequences per lane), each item with its query's profile and score row,
+  // on the auxiliary stream and enqueued before the persistent batched
+  // kernel, so that its workgroups take CUs first and the batched kernel's
+  // fill the rest (the batched kernel holds every CU it gets until its list
+  // is drained); joined before the rescoring.  Sequences at the rescoring
+  // limit join the list the batched kernel fills.
+  const bool vlong = B.n_long_items > 0;
+  if (vlong) {
+    if ((e = hipEventRecord(db->ev_fork, s)) != hipSuccess ||
+        (e = hipStreamWaitEvent(db->aux_stream, db->ev_fork, 0)) != hipSuccess)
+      return hip_fail(e, "stream fork");
     IntraPairArgs la{};
     la.res = db->d->res.p;
     la.offs = db->d->offs.p;
@@ -1283,10 +1287,12 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
     la.out = B.d_out;
     la.flag_count = db->flags.p;
     la.flag_list = flag_list(db);
-    const int tl = time_begin(db, kTimeIntra, s);
-    if ((e = launch_intra_pairs(B.RRp, B.W2p, B.grid_long, la, s)) != hipSuccess)
+    const int tl = time_begin(db, kTimeIntra, db->aux_stream);
+    if ((e = launch_intra_pairs(B.RRp, B.W2p, B.grid_long, la, db->aux_stream)) != hipSuccess)
       return hip_fail(e, "long-pair kernel");
-    time_end(db, tl, s);
+    time_end(db, tl, db->aux_stream);
+    if ((e = hipEventRecord(db->ev_join, db->aux_stream)) != hipSuccess)
+      return hip_fail(e, "event");
   }
   if (db->d->plan.n_bins + db->d->plan.n_long_bins > 0) {
     BatchArgs ba{};
@@ -1312,6 +1318,8 @@ int enqueue_batch_kernels(Searcher* db, hipStream_t s) {
       return hip_fail(e, "batched inter-task kernel");
     time_end(db, ti, s);
   }
+  if (vlong && (e = hipStreamWaitEvent(s, db->ev_join, 0)) != hipSuccess)
+    return hip_fail(e, "stream join");
   {  // exact rescoring of what both packed kernels flagged
     IntraArgs ra = ia;
     ra.items = flag_list(db);
