@@ -1849,26 +1849,14 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   if ((e = db->q_stage.reserve((size_t)query_len)) != hipSuccess ||
       (e = db->out_stage.reserve((size_t)n)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("staging allocation: ") + hipGetErrorString(e));
-  std::vector<int32_t> gpu_scores;
   std::vector<int64_t> cum;   // cells of the bins before bin b, b = 0 .. n_bins
-  std::vector<uint8_t> host_done;   // per slot: scored by a host thread
   cpu::Profile prof;
   try {
-    gpu_scores.resize((size_t)n);
-    cum.assign((size_t)n_bins + 1, 0);
-    host_done.assign((size_t)n_bins * SW_BIN_SEQS, 0);
+    cum.resize((size_t)n_bins + 1);
+    for (int64_t b = 0; b <= n_bins; ++b) cum[(size_t)b] = D.bin_res_cum[(size_t)b] * query_len;
     cpu::build_profile(query, query_len, matrix, &prof);
   } catch (...) {
     return fail(SW_ENOMEM, "host allocation failed");
-  }
-  for (int64_t b = 0; b < n_bins; ++b) {
-    const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
-    int64_t res = 0;
-    for (int k = 0; k < SW_BIN_SEQS; ++k) {
-      const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
-      if (sid >= 0) res += D.h_offs[(size_t)sid + 1] - D.h_offs[(size_t)sid];
-    }
-    cum[(size_t)b + 1] = cum[(size_t)b] + res * query_len;
   }
   hipStream_t s = db->own_stream;
   if ((e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
@@ -1902,8 +1890,11 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   std::atomic<int64_t> cpu_cells{0}, cpu_seqs{0};
   std::atomic<int64_t> cpu_ns{0};
   std::vector<std::thread> pool;
-  auto worker = [&]() {
+  // each host thread's {sequence, score} results, applied after the GPU's
+  std::vector<std::vector<int2>> host_res((size_t)threads);
+  auto worker = [&](int t) {
     cpu::Workspace w;
+    std::vector<int2>& mine = host_res[(size_t)t];
     int64_t cells = 0, seqs = 0, ns = 0;
     while (!gpu_done.load(std::memory_order_relaxed)) {
       const int64_t slot = back.fetch_sub(1) - 1;
@@ -1926,8 +1917,8 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
         gpu_done = true;          // stops the other host threads too
         break;
       }
-      out_scores[sid] = cpu::score(prof, D.h_res.data() + at, len, gap_open, gap_extend, &w);
-      host_done[(size_t)slot] = 1;
+      mine.push_back(make_int2(sid, cpu::score(prof, D.h_res.data() + at, len, gap_open,
+                                               gap_extend, &w)));
       ns += std::chrono::duration_cast<std::chrono::nanoseconds>(clock::now() - now).count();
       cells += c;
       ++seqs;
@@ -1937,7 +1928,7 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
     cpu_ns += ns;
   };
   try {
-    for (int t = 0; t < threads; ++t) pool.emplace_back(worker);
+    for (int t = 0; t < threads; ++t) pool.emplace_back(worker, t);
   } catch (...) {
     gpu_done = true;   // no more host work
   }
@@ -2003,24 +1994,18 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   gpu_done = true;
   if (!joined)
     for (auto& t : pool) t.join();
+  // the GPU's scores straight into the caller's array, then the host's on
+  // top: the GPU scored the bins it took and the long list, a host thread
+  // every slot outside the GPU's bins (and perhaps some inside, with the
+  // same scores), so every entry ends up written by a side that scored it
   if (rc == SW_OK &&
-      (e = hipMemcpyAsync(gpu_scores.data(), db->out_stage.p, (size_t)n * 4, hipMemcpyDeviceToHost,
+      (e = hipMemcpyAsync(out_scores, db->out_stage.p, (size_t)n * 4, hipMemcpyDeviceToHost,
                           s)) != hipSuccess)
     rc = hip_fail(e, "score download");
   if ((e = hipStreamSynchronize(s)) != hipSuccess && rc == SW_OK) rc = hip_fail(e, "search");
   if (rc != SW_OK) return rc;
-  // GPU share: the bins it took (except the slots a host thread scored,
-  // which hold the same scores already) and the long list; every slot
-  // outside the GPU's bins was scored by a host thread
-  for (int64_t b = 0; b < front.load(); ++b) {
-    const int64_t slot0 = D.h_bins[(size_t)b * 4 + 3];
-    for (int k = 0; k < SW_BIN_SEQS; ++k) {
-      if (host_done[(size_t)(b * SW_BIN_SEQS + k)]) continue;
-      const int32_t sid = D.h_slots[(size_t)(slot0 + k)];
-      if (sid >= 0) out_scores[sid] = gpu_scores[(size_t)sid];
-    }
-  }
-  for (int32_t sid : D.long_ids) out_scores[sid] = gpu_scores[(size_t)sid];
+  for (const auto& mine : host_res)
+    for (const int2& r : mine) out_scores[r.x] = r.y;
   // running averages of both sides' rates for the next plan
   const double gpu_s = std::chrono::duration<double>(t_gpu1 - t_gpu0).count();
   const double gpu_short = cells_all - (double)cpu_cells.load();
