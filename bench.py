@@ -508,7 +508,7 @@ def batched_leg(db, scale, replays=3):
                     "the schedule fitted to the pairs" % len(times)}
 
 
-def served_leg(db, scale, n_requests, qps, slots=4, max_batch=8, timeout_s=None):
+def served_leg(db, scale, n_requests, qps, slots=4, max_batch=16, timeout_s=None):
     import numpy as np
     import swinputs
     from paper_2203_11100_amd import serve

@@ -24,6 +24,10 @@ whole query aligned inside the database sequence, whose overhangs are free),
 are maxima over chains with different end costs and no floor at 0:
 sw_bruteforce_mode, sw_gotoh_mode and cpu.score_mode/search_mode.
 
+The alignment itself (an M/I/D string placed at its first residues, scored
+by alignment_score from the same definition) is recovered by walking the
+H/E/F tables back from that end: sw_gotoh_traceback.
+
 Three implementations, each written from that definition:
   * sw_bruteforce  - enumerates every chain (tiny inputs only);
   * sw_gotoh       - Gotoh's H/E/F recurrence in plain Python;
@@ -31,10 +35,10 @@ Three implementations, each written from that definition:
                      threaded over database sequences; the timed CPU baseline
                      and the parity source for full-size workloads.
 """
-from .sw_ref import (GLOBAL, SEMIGLOBAL, gap_cost, sw_bruteforce, sw_bruteforce_end,
-                     sw_bruteforce_mode, sw_bruteforce_table, sw_gotoh, sw_gotoh_end,
-                     sw_gotoh_mode)
+from .sw_ref import (GLOBAL, SEMIGLOBAL, alignment_score, gap_cost, sw_bruteforce,
+                     sw_bruteforce_end, sw_bruteforce_mode, sw_bruteforce_table, sw_gotoh,
+                     sw_gotoh_end, sw_gotoh_mode, sw_gotoh_traceback)
 
-__all__ = ["GLOBAL", "SEMIGLOBAL", "gap_cost", "sw_bruteforce", "sw_bruteforce_end",
-           "sw_bruteforce_mode", "sw_bruteforce_table", "sw_gotoh", "sw_gotoh_end",
-           "sw_gotoh_mode"]
+__all__ = ["GLOBAL", "SEMIGLOBAL", "alignment_score", "gap_cost", "sw_bruteforce",
+           "sw_bruteforce_end", "sw_bruteforce_mode", "sw_bruteforce_table", "sw_gotoh",
+           "sw_gotoh_end", "sw_gotoh_mode", "sw_gotoh_traceback"]

@@ -243,3 +243,104 @@ def sw_gotoh_mode(a: Sequence[int], b: Sequence[int], S, gap_open: int, gap_exte
     if mode == GLOBAL or n == 0:
         return int(H[m][n])
     return int(max(H[m][j] for j in range(1, n + 1)))
+
+
+# ---------------------------------------------------------------- traceback
+# The alignment behind a local score (SW# computes alignments, section 2.3,
+# and a search tool reports them for its best hits).  An alignment is a
+# string over M (query residue a_i against database residue b_j), I (a query
+# residue against a gap) and D (a database residue against a gap), starting
+# at (q_begin, s_begin) and consuming residues left to right; its score is
+# the sum of S over the M columns minus w(k) for every maximal run of k I's
+# and every maximal run of k D's (a run of I's next to a run of D's is two
+# gaps, as between two matched pairs of a chain).
+
+
+def alignment_score(a: Sequence[int], b: Sequence[int], S, gap_open: int, gap_extend: int,
+                    q_begin: int, s_begin: int, ops: str) -> Tuple[int, int, int]:
+    """Score of the alignment `ops` placed at (q_begin, s_begin), and the
+    0-based indices (q_end, s_end) of the last query and database residues
+    it consumes.  Raises ValueError if it runs past either sequence."""
+    i, j, score = q_begin, s_begin, 0
+    run_op, run_len = "", 0
+
+    def close():
+        return -gap_cost(run_len, gap_open, gap_extend) if run_op in ("I", "D") else 0
+
+    for op in ops:
+        if op != run_op:
+            score += close()
+            run_op, run_len = op, 0
+        run_len += 1
+        if op == "M":
+            if i >= len(a) or j >= len(b):
+                raise ValueError("alignment runs past a sequence")
+            score += int(S[a[i]][b[j]])
+            i += 1
+            j += 1
+        elif op == "I":
+            if i >= len(a):
+                raise ValueError("alignment runs past the query")
+            i += 1
+        elif op == "D":
+            if j >= len(b):
+                raise ValueError("alignment runs past the database sequence")
+            j += 1
+        else:
+            raise ValueError("unknown operation %r" % op)
+    score += close()
+    return score, i - 1, j - 1
+
+
+def sw_gotoh_traceback(a: Sequence[int], b: Sequence[int], S, gap_open: int,
+                       gap_extend: int) -> Tuple[int, int, int, int, int, str]:
+    """An optimal local alignment ending at the end of sw_gotoh_end.
+
+    The recurrence of sw_gotoh over full H, E and F tables, then a walk back
+    from the end cell (i, j) (1-based) in three states: in H, stop where
+    H(i, j) = 0, else step to (i-1, j-1) emitting M if H came from the
+    diagonal, else enter F, else E (the first source in that order that
+    equals H); in F emit I and step up, back to H if F came from H(i-1, j) -
+    open, else stay in F; in E emit D and step left likewise.  Returns
+    (score, q_begin, s_begin, q_end, s_end, ops) with 0-based inclusive
+    residue indices; a score of 0 has no alignment: (0, -1, -1, -1, -1, "").
+    """
+    m, n = len(a), len(b)
+    NEG = -math.inf
+    H = [[0] * (n + 1) for _ in range(m + 1)]
+    E = [[NEG] * (n + 1) for _ in range(m + 1)]
+    F = [[NEG] * (n + 1) for _ in range(m + 1)]
+    best, end = 0, None
+    for i in range(1, m + 1):
+        for j in range(1, n + 1):
+            E[i][j] = max(E[i][j - 1] - gap_extend, H[i][j - 1] - gap_open)
+            F[i][j] = max(F[i - 1][j] - gap_extend, H[i - 1][j] - gap_open)
+            H[i][j] = max(0, H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]),
+                          E[i][j], F[i][j])
+            if H[i][j] > 0 and (H[i][j] > best or (H[i][j] == best and (j, i) < end)):
+                best, end = H[i][j], (j, i)
+    if best == 0:
+        return 0, -1, -1, -1, -1, ""
+    j, i = end
+    ops = []
+    state = "H"
+    while True:
+        if state == "H":
+            if H[i][j] == 0:
+                break
+            if H[i][j] == H[i - 1][j - 1] + int(S[a[i - 1]][b[j - 1]]):
+                ops.append("M")
+                i, j = i - 1, j - 1
+            elif H[i][j] == F[i][j]:
+                state = "F"
+            else:
+                state = "E"
+        elif state == "F":
+            ops.append("I")
+            state = "H" if F[i][j] == H[i - 1][j] - gap_open else "F"
+            i -= 1
+        else:
+            ops.append("D")
+            state = "H" if E[i][j] == H[i][j - 1] - gap_open else "E"
+            j -= 1
+    return int(best), i, j, end[1] - 1, end[0] - 1, "".join(reversed(ops))

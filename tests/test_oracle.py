@@ -307,6 +307,73 @@ def test_end_embedded_copy_closed_form():
             (int(sum(int(B62[c, c]) for c in qs)), len(qs) - 1, min(len(x), 10) + len(qs) - 1)
 
 
+# ------------------------------------------------------------------ traceback
+def test_alignment_score_hand_cases():
+    """The score of an M/I/D string by hand: BLOSUM62 W/W = 11, G/W = -2,
+    A/A = 4; gaps 10(2): w(1) = 10, w(3) = 14."""
+    e = swinputs.encode
+    # WWGWW vs WWWW: MMIMM = 4 x 11 - w(1) = 34, ending at (4, 3)
+    assert oracle.alignment_score(e("WWGWW"), e("WWWW"), B62, 10, 2, 0, 0, "MMIMM") == (34, 4, 3)
+    # the same residues all matched: MMMM over WWGW/WWWW = 33 - 2 = 31
+    assert oracle.alignment_score(e("WWGWW"), e("WWWW"), B62, 10, 2, 0, 0, "MMMM") == (31, 3, 3)
+    # a run of three D's is one gap of 3 (14), not three of 1 (30)
+    assert oracle.alignment_score(e("AA"), e("AGGGA"), B62, 10, 2, 0, 0, "MDDDM") == (8 - 14, 1, 4)
+    # I next to D: two gaps of 1
+    assert oracle.alignment_score(e("AGA"), e("AGA"), B62, 10, 2, 0, 0, "MIDM") == (8 - 20, 2, 2)
+    # placed after leading residues
+    assert oracle.alignment_score(e("KAA"), e("GGAA"), B62, 10, 2, 1, 2, "MM") == (8, 2, 3)
+    with pytest.raises(ValueError):
+        oracle.alignment_score(e("AA"), e("A"), B62, 10, 2, 0, 0, "MM")
+    with pytest.raises(ValueError):
+        oracle.alignment_score(e("AA"), e("AA"), B62, 10, 2, 0, 0, "MMX")
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_traceback_is_an_optimal_alignment_bruteforce(seed):
+    """The traceback's alignment, scored from its definition, reaches the
+    brute-force optimum, ends at the brute-force end (smallest (j, i) among
+    optimal chains) and starts and ends with a matched pair; a score of 0
+    has no alignment."""
+    rng = np.random.default_rng(300 + seed)
+    cases = list(_tie_heavy_cases(200 + seed, 30)) + list(_tiny_cases(250 + seed, 20))
+    for a, b, S in cases:
+        for idx in rng.choice(len(GAPS_SMALL), 5, replace=False):
+            o, e = GAPS_SMALL[idx]
+            best, qe, de = oracle.sw_bruteforce_end(a, b, S, o, e)
+            score, qb, sb, qe2, de2, ops = oracle.sw_gotoh_traceback(a, b, S, o, e)
+            assert (score, qe2, de2) == (best, qe, de), (a, b, S, o, e)
+            if best == 0:
+                assert (qb, sb, ops) == (-1, -1, "")
+                continue
+            assert ops[0] == "M" and ops[-1] == "M"
+            assert oracle.alignment_score(a, b, S, o, e, qb, sb, ops) == (best, qe, de)
+
+
+def test_traceback_hand_and_closed_forms():
+    """WWGWW / WWWW: the G is skipped (34, MMIMM); an embedded copy of the
+    query aligns ungapped from the copy's first residue; a copy with one
+    residue deleted from the database side aligns with a single I."""
+    e = swinputs.encode
+    assert oracle.sw_gotoh_traceback(e("WWGWW"), e("WWWW"), B62, 10, 2) == \
+        (34, 0, 0, 4, 3, "MMIMM")
+    rng = np.random.default_rng(12)
+    for _ in range(10):
+        m = int(rng.integers(20, 50))
+        q = swinputs.random_residues(m, rng)
+        x = swinputs.random_residues(int(rng.integers(0, 40)), rng)
+        y = swinputs.random_residues(int(rng.integers(0, 40)), rng)
+        diag = int(sum(int(B62[c, c]) for c in q))
+        assert oracle.sw_gotoh_traceback(q, np.concatenate([x, q, y]), B62, 10, 2) == \
+            (diag, 0, len(x), m - 1, len(x) + m - 1, "M" * m)
+    # W-runs around a deleted residue: WWWWWWKWWWWWW against WWWWWWWWWWWW
+    # loses the K (w(1) = 10) and keeps 12 W/W pairs (132): 122 with one I
+    q = e("WWWWWWKWWWWWW")
+    t = e("WWWWWWWWWWWW")
+    score, qb, sb, qe, de, ops = oracle.sw_gotoh_traceback(q, t, B62, 10, 2)
+    assert score == 122 and ops.count("I") == 1 and ops.count("D") == 0 and ops.count("M") == 12
+    assert oracle.alignment_score(q, t, B62, 10, 2, qb, sb, ops) == (122, qe, de)
+
+
 def test_search_end_matches_per_sequence():
     rng = np.random.default_rng(12)
     lengths = rng.integers(0, 300, 400)
