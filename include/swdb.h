@@ -223,6 +223,48 @@ int sw_search_topk_async(sw_db* db, const uint8_t* d_query, int32_t query_len,
                          const int8_t* matrix, int32_t gap_open, int32_t gap_extend, int32_t k,
                          int32_t* d_out_scores, sw_hit* d_hits, void* hip_stream);
 
+/* sw_traceback: the alignments themselves, for chosen database sequences
+ * (a search's best hits): for each, an optimal local alignment of the query
+ * with the sequence (paper section 2.3: SW# computes alignments, and a
+ * search reports them for its best hits), ending at the end sw_search_topk
+ * reports.  The exact 32-bit intra-task kernel recomputes each sequence's
+ * matrix, keeping one traceback code per cell in device memory (query
+ * length rounded up to 512 bytes per sequence residue; sequences go in
+ * groups of up to 1 GiB of codes); the codes come back to the host, where
+ * one thread per sequence walks back from the end.  Of several optimal
+ * alignments it returns the one that, walking back, prefers a matched pair,
+ * then a query residue against a gap, then a database residue against a
+ * gap, and ends a gap at the first place it can.
+ *   query, matrix : host, as sw_search.
+ *   seqs      : host, n_items database sequence indices (any order,
+ *               repeats allowed), 0 <= n_items <= SW_MAX_TOPK.
+ *   out       : host, sw_alignment[n_items], in the order of seqs.
+ *   ops       : host, uint32_t[ops_cap]: every alignment's operations in
+ *               runs, (length << 2) | op with op 0 = M (a query residue
+ *               against a database residue), 1 = I (a query residue against
+ *               a gap), 2 = D (a database residue against a gap); alignment
+ *               t's runs are ops[out[t].ops_offset .. + out[t].n_ops).  At
+ *               most query_len + the sequence's length runs per alignment.
+ *   ops_used  : host, or NULL: the runs all alignments take (also when
+ *               ops_cap is too small: then SW_ERANGE and nothing written).
+ * A score of 0 has no alignment: begins and ends -1, no runs.  A sequence
+ * whose codes would exceed 4 GiB returns SW_ERANGE; codes that do not form
+ * a path (a fault) return SW_EDEVICE.  Synchronous. */
+typedef struct sw_alignment {
+  int32_t seq;          /* database sequence index */
+  int32_t score;        /* the alignment's score (the sequence's search score) */
+  int32_t query_begin;  /* 0-based first and last query positions, or -1 */
+  int32_t query_end;
+  int32_t db_begin;     /* 0-based first and last database-sequence positions */
+  int32_t db_end;
+  int64_t ops_offset;   /* first run in ops */
+  int32_t n_ops;        /* runs */
+  int32_t reserved;
+} sw_alignment;
+int sw_traceback(sw_db* db, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                 int32_t gap_open, int32_t gap_extend, const int32_t* seqs, int32_t n_items,
+                 sw_alignment* out, uint32_t* ops, int64_t ops_cap, int64_t* ops_used);
+
 /* ---------------------------------------------------------- hybrid search
  * sw_search_hybrid: one query against every database sequence with host
  * cores and the GPU at once (paper section 2.3: SW#db uses CPUs and GPUs

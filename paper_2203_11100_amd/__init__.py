@@ -23,7 +23,7 @@ __all__ = ["Database", "Context", "SwError", "plan", "pack", "host_search", "SW_
            "SW_MIN_BIN_LEN", "SW_DEFAULT_LONG_THRESHOLD", "SW_OPT_TIMING", "SW_OPT_SAT_LIMIT",
            "SW_OPT_ROWS", "SW_OPT_WAVES", "SW_OPT_INTRA_ROWS", "SW_OPT_INTRA_WAVES", "SW_OPT_GRAPHS",
            "SW_OPT_HYBRID_SHARE", "SW_OPT_OFFLOAD_BINS",
-           "SW_MAX_TOPK", "HIT_DTYPE", "SW_MODE_LOCAL", "SW_MODE_GLOBAL", "SW_MODE_SEMIGLOBAL",
+           "SW_MAX_TOPK", "HIT_DTYPE", "ALIGNMENT_DTYPE", "SW_MODE_LOCAL", "SW_MODE_GLOBAL", "SW_MODE_SEMIGLOBAL",
            "MODES"]
 
 # alignment operation names accepted by Database.search_mode
@@ -33,6 +33,11 @@ MODES = {"local": SW_MODE_LOCAL, "global": SW_MODE_GLOBAL, "semiglobal": SW_MODE
 # when the score is 0)
 HIT_DTYPE = np.dtype([("seq", np.int32), ("score", np.int32), ("query_end", np.int32),
                       ("db_end", np.int32)])
+# sw_alignment
+ALIGNMENT_DTYPE = np.dtype([("seq", np.int32), ("score", np.int32), ("query_begin", np.int32),
+                            ("query_end", np.int32), ("db_begin", np.int32), ("db_end", np.int32),
+                            ("ops_offset", np.int64), ("n_ops", np.int32), ("reserved", np.int32)])
+_OPS = "MID"
 
 
 def _ptr(a) -> Optional[int]:
@@ -255,6 +260,40 @@ class Database:
         _native.check(_native.lib().sw_search_topk(self._h, _ptr(q), len(q), _ptr(m), gap_open,
                                                    gap_extend, int(k), _ptr(out), _ptr(hits)))
         return (hits, out) if scores else hits
+
+    def traceback(self, query, matrix, gap_open: int = 10, gap_extend: int = 2, seqs=()):
+        """Optimal local alignments of the query with the database sequences
+        `seqs` (sw_traceback), in that order: a list of dicts with seq,
+        score, query_begin/_end, db_begin/_end (0-based inclusive, -1 for a
+        score of 0) and ops, the alignment as a string over M (query residue
+        against database residue), I (query residue against a gap) and D
+        (database residue against a gap)."""
+        q = _u8(query)
+        m = _matrix(matrix)
+        ids = np.ascontiguousarray(seqs, dtype=np.int32)
+        out = np.zeros(len(ids), dtype=ALIGNMENT_DTYPE)
+        # room for every run (the library checks the indices themselves)
+        ok = (ids >= 0) & (ids < self.n_seqs)
+        lens = np.where(ok, self._lengths()[np.where(ok, ids, 0)], 0) if len(ids) else \
+            np.zeros(0, np.int64)
+        cap = int((lens + len(q)).sum())
+        ops = np.zeros(max(cap, 1), dtype=np.uint32)
+        used = ctypes.c_int64()
+        _native.check(_native.lib().sw_traceback(self._h, _ptr(q), len(q), _ptr(m), gap_open,
+                                                 gap_extend, _ptr(ids), len(ids), _ptr(out),
+                                                 _ptr(ops), cap, ctypes.byref(used)))
+        res = []
+        for a in out:
+            runs = ops[int(a["ops_offset"]):int(a["ops_offset"]) + int(a["n_ops"])]
+            res.append({k: int(a[k]) for k in ("seq", "score", "query_begin", "query_end",
+                                               "db_begin", "db_end")})
+            res[-1]["ops"] = "".join(_OPS[int(r) & 3] * (int(r) >> 2) for r in runs)
+        return res
+
+    def _lengths(self):
+        if getattr(self, "_lens", None) is None:
+            self._lens = np.diff(self._offs)
+        return self._lens
 
     def search_topk_async(self, d_query, matrix, gap_open: int, gap_extend: int, k: int, d_out,
                           d_hits, stream=None):

@@ -92,6 +92,7 @@ SIGNATURES = {
     "sw_search_async": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
     "sw_search_async_noalloc": (ctypes.c_int, [P, P, I32, P, I32, I32, P, P]),
     "sw_search_topk": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P]),
+    "sw_traceback": (ctypes.c_int, [P, P, I32, P, I32, I32, P, I32, P, P, I64, P]),
     "sw_search_topk_async": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P, P, P]),
     "sw_search_hybrid": (ctypes.c_int, [P, P, I32, P, I32, I32, I32, P,
                                         ctypes.POINTER(HybridStats)]),

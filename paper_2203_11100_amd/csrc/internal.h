@@ -106,6 +106,12 @@ struct IntraArgs {
   int32_t mode;               // SW_MODE_*: local (with or without ends), global,
                               // semi-global (single query q0)
   int32_t m;                  // query length (global and semi-global)
+  uint8_t* dir;               // non-null (with ends): the traceback codes of every
+                              // cell, item it's at dir + dir_off[it], column-major
+                              // with dir_ld bytes (>= the query's padded rows) per
+                              // column; see k_intra.hip
+  const int64_t* dir_off;
+  int64_t dir_ld;
 };
 
 // Global / semi-global inter-task kernel (k_modes.hip): one database

@@ -129,15 +129,29 @@ __device__ __forceinline__ bool end_before(int s, int c, int r, int s2, int c2, 
 // (so the lane below reads the border as its diagonal), and the lane holding
 // the query's last row reads the score from the sequence's own columns in
 // the last pass.
-enum { kVarScore = 0, kVarEnds = 1, kVarGlobal = 2, kVarSemi = 3 };
+//
+// kVarTrace: kVarEnds plus one traceback code per cell (i, j), so that the
+// host can walk an optimal alignment back from the end: bits 0-1 say where
+// H(i, j) came from (0: it is 0, the alignment starts after this cell; 1:
+// the diagonal H(i-1, j-1) + S; 3: F(i, j); 2: E(i, j); the first that
+// equals H in the order 0, diagonal, F, E), bit 2 that E(i, j+1) comes from
+// opening a gap after H(i, j) rather than extending E(i, j), bit 3 the same
+// for F(i+1, j) (opening preferred on ties).  The clamped E and F give the
+// same choices wherever the walk can be: it enters E or F only where they
+// are positive, and a positive value never comes from a clamped 0.  Codes
+// are bytes [column][row] (row = 0-based query position), one 8-, 4- or
+// 2-byte store per lane and step for its R rows, written for the sequence's
+// own columns only.
+enum { kVarScore = 0, kVarEnds = 1, kVarGlobal = 2, kVarSemi = 3, kVarTrace = 4 };
 constexpr int kNegInf = -(1 << 29);
 
 __device__ __forceinline__ int gapw(int k, int go, int ge) { return k == 0 ? 0 : go + (k - 1) * ge; }
 
 template <int R, int W2, int V>
 __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
-  constexpr bool kEnds = V == kVarEnds;
-  constexpr bool kLocal = V == kVarScore || V == kVarEnds;
+  constexpr bool kTrace = V == kVarTrace;
+  constexpr bool kEnds = V == kVarEnds || kTrace;
+  constexpr bool kLocal = V == kVarScore || kEnds;
   constexpr int ROWS = 64 * R;   // query rows per pass
   __shared__ __align__(16) int8_t lprof_all[W2][kIntraCodes * ROWS];
   __shared__ int lbest[W2];
@@ -162,6 +176,7 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
     const int64_t b0 = a.offs[sid];
     const int n = (int)(a.offs[sid + 1] - b0);
     const uint8_t* __restrict__ bseq = a.res + b0;
+    uint8_t* __restrict__ dir = kTrace ? a.dir + a.dir_off[it] : nullptr;
     // supersteps per pass: n + 63 steps, at least kSkew*W2 (see above)
     const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
     const int T_total = q_last * C2 + kSkew * w_last + C2;
@@ -239,10 +254,19 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
           hdiag = hup;
           int F = fup;
           const int col = c * 64 + tau - lane;    // this step's column
+          uint32_t tcode[(R + 3) / 4];             // kTrace: this step's codes
+#pragma unroll
+          for (int x = 0; x < (R + 3) / 4; ++x) tcode[x] = 0;
           if (kLocal || col >= 0) {
 #pragma unroll
             for (int k = 0; k < R; ++k) {
-              const int h = imax(imax(hd + prof[k], E[k]), F);
+              const int d = hd + prof[k];
+              const int h = imax(imax(d, E[k]), F);
+              if constexpr (kTrace) {
+                const uint32_t src = h == 0 ? 0u : h == d ? 1u : h == F ? 3u : 2u;
+                const uint32_t op = (h - go >= E[k] - ge ? 4u : 0u) | (h - go >= F - ge ? 8u : 0u);
+                tcode[k >> 2] |= (src | op) << (8 * (k & 3));
+              }
               hd = H[k];
               H[k] = h;
               if constexpr (kEnds) {
@@ -257,6 +281,18 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
               } else {
                 E[k] = imax(E[k] - ge, t);
                 F = imax(F - ge, t);
+              }
+            }
+          }
+          if constexpr (kTrace) {
+            if (col >= 0 && col < n) {
+              uint8_t* at = dir + (size_t)col * a.dir_ld + (size_t)top;
+              if constexpr (R == 8) {
+                *reinterpret_cast<uint2*>(at) = make_uint2(tcode[0], tcode[1]);
+              } else if constexpr (R == 4) {
+                *reinterpret_cast<uint32_t*>(at) = tcode[0];
+              } else {
+                *reinterpret_cast<uint16_t*>(at) = (uint16_t)tcode[0];
               }
             }
           }
@@ -597,6 +633,8 @@ hipError_t launch_rw(int grid, const IntraArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_intra_i32<R, W2, kVarGlobal>), dim3(grid), dim3(64 * W2), 0, s, a);
   else if (a.mode == SW_MODE_SEMIGLOBAL)
     hipLaunchKernelGGL((k_intra_i32<R, W2, kVarSemi>), dim3(grid), dim3(64 * W2), 0, s, a);
+  else if (a.ends && a.dir)
+    hipLaunchKernelGGL((k_intra_i32<R, W2, kVarTrace>), dim3(grid), dim3(64 * W2), 0, s, a);
   else if (a.ends)
     hipLaunchKernelGGL((k_intra_i32<R, W2, kVarEnds>), dim3(grid), dim3(64 * W2), 0, s, a);
   else

@@ -216,6 +216,10 @@ struct Searcher {
   DevBuf<int32_t> counter;          // work-queue head of the batched kernel
   DevBuf<int32_t> topk;             // top-k selection state, candidates, hit items
   DevBuf<int4> hits_stage;          // hit list of host-buffer top-k calls
+  DevBuf<uint8_t> trace_dir;        // traceback codes of one group of sequences
+  DevBuf<int2> trace_items;         // {sequence, 0} of the group
+  DevBuf<int64_t> trace_off;        // each item's code offset
+  DevBuf<int4> trace_ends;          // each item's {sequence, score, query end, db end}
   DevBuf<int32_t> mprof;            // int32 strip profile of global / semi-global searches
   DevBuf<int2> rb_mode;             // their boundary rows, 8 bytes per short-bin cell column
   hipStream_t own_stream = nullptr; // host-buffer calls and batch graphs
@@ -273,6 +277,8 @@ void release_searcher(Searcher* db) {
   db->out_stage.release();
   db->batch.release(); db->rb_batch.release(); db->counter.release();
   db->topk.release(); db->hits_stage.release(); db->mprof.release(); db->rb_mode.release();
+  db->trace_dir.release(); db->trace_items.release(); db->trace_off.release();
+  db->trace_ends.release();
   if (db->users.caller_pending) (void)hipEventSynchronize(db->ev_caller);
   db->users.caller_pending = false;
   for (hipEvent_t* e : {&db->ev_fork, &db->ev_join, &db->ev_in, &db->ev_out, &db->ev_caller,
@@ -310,6 +316,7 @@ void bind_buffers(Searcher* S) {
   S->out_stage.users = u;
   S->rb_batch.users = S->counter.users = S->flags.users = u;
   S->topk.users = S->hits_stage.users = u;
+  S->trace_dir.users = S->trace_items.users = S->trace_off.users = S->trace_ends.users = u;
   S->mprof.users = S->rb_mode.users = u;
   BatchPlan& B = S->batch;
   B.pairs.users = u; B.qdesc.users = u; B.items.users = u; B.long_items.users = u;
@@ -1732,6 +1739,222 @@ static int impl_search(swdb::Searcher* db, const uint8_t* query, int32_t query_l
   return SW_OK;
 }
 
+namespace swdb {
+namespace {
+
+// Device bytes of traceback codes per launch: the sequences are taken in
+// groups whose codes fit (one sequence alone may have up to kTraceMaxBox).
+constexpr int64_t kTraceGroupBytes = int64_t(1) << 30;
+constexpr int64_t kTraceMaxBox = int64_t(4) << 30;
+
+// Walks an optimal alignment back from its end (0-based q_end, db_end)
+// through the codes of k_intra_i32's traceback variant ([column][row] bytes,
+// ld per column) and appends it, first operation first, as runs
+// (length << 2 | op) with op 0 = M, 1 = I (query residue against a gap), 2 =
+// D (database residue against a gap).  Returns false on codes that do not
+// form a path (never for the kernel's codes).
+bool walk_alignment(const uint8_t* dir, int64_t ld, int32_t q_end, int32_t db_end,
+                    int32_t* q_begin, int32_t* db_begin, std::vector<uint32_t>* runs) {
+  std::vector<uint8_t> rev;
+  int64_t i = (int64_t)q_end + 1, j = (int64_t)db_end + 1;   // 1-based cell
+  int state = 0;                                              // 0 H, 1 F, 2 E
+  const int64_t bound = 2 * (i + j) + 4;
+  for (int64_t step = 0; step <= bound; ++step) {
+    if (state != 0 && (i < 1 || j < 1)) return false;
+    // H is 0 on the borders (row 0, column 0): the alignment starts there too
+    const uint8_t c = state == 0 && (i < 1 || j < 1) ? 0 : dir[(j - 1) * ld + (i - 1)];
+    if (state == 0) {
+      const int src = c & 3;
+      if (src == 0) {
+        *q_begin = (int32_t)i;
+        *db_begin = (int32_t)j;
+        for (size_t x = rev.size(); x-- > 0;) {
+          const uint32_t op = rev[x];
+          if (!runs->empty() && (runs->back() & 3u) == op) runs->back() += 4u;
+          else runs->push_back(4u | op);
+        }
+        return true;
+      }
+      if (src == 1) { rev.push_back(0); --i; --j; }
+      else state = src == 3 ? 1 : 2;
+    } else if (state == 1) {
+      rev.push_back(1);
+      if (i < 2) return false;
+      state = (dir[(j - 1) * ld + (i - 2)] >> 3) & 1 ? 0 : 1;
+      --i;
+    } else {
+      rev.push_back(2);
+      if (j < 2) return false;
+      state = (dir[(j - 2) * ld + (i - 1)] >> 2) & 1 ? 0 : 2;
+      --j;
+    }
+  }
+  return false;
+}
+
+}  // namespace
+}  // namespace swdb
+
+static int impl_traceback(swdb::Searcher* db, const uint8_t* query, int32_t query_len,
+                          const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
+                          const int32_t* seqs, int32_t n_items, sw_alignment* out, uint32_t* ops,
+                          int64_t ops_cap, int64_t* ops_used) {
+  using namespace swdb;
+  int rc = validate_search(db, query, query_len, matrix, gap_open, gap_extend, matrix);
+  if (rc != SW_OK) return rc;
+  if (n_items < 0 || n_items > SW_MAX_TOPK)
+    return fail(SW_ERANGE, "n_items must be 0..SW_MAX_TOPK");
+  if (n_items > 0 && (!seqs || !out)) return fail(SW_EINVAL, "seqs or out is NULL");
+  if (ops_cap < 0 || (ops_cap > 0 && !ops)) return fail(SW_EINVAL, "ops is NULL or ops_cap < 0");
+  const int64_t n_seqs = db->d->n_seqs;
+  for (int32_t t = 0; t < n_items; ++t)
+    if (seqs[t] < 0 || seqs[t] >= n_seqs)
+      return fail(SW_EINVAL, "sequence index out of range at item " + std::to_string(t));
+  for (int32_t i = 0; i < query_len; ++i)
+    if (query[i] >= SW_ALPHA) return fail(SW_EINVAL, "query code >= 24 at position " + std::to_string(i));
+  const int64_t ld = intra_rows_pad(std::max(query_len, 1));
+  const std::vector<int64_t>& offs = db->d->h_offs;
+  for (int32_t t = 0; t < n_items; ++t) {
+    const int64_t box = (offs[(size_t)seqs[t] + 1] - offs[(size_t)seqs[t]]) * ld;
+    if (box > kTraceMaxBox)
+      return fail(SW_ERANGE, "traceback codes of sequence " + std::to_string(seqs[t]) + " (" +
+                                 std::to_string(box) + " bytes) exceed 4 GiB");
+  }
+  std::unique_lock<std::mutex> lk(db->mtx, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(SW_EBUSY, "another call is running on this handle");
+  DeviceGuard g(db->d->device);
+  std::vector<int4> ends((size_t)n_items);
+  std::vector<std::vector<uint32_t>> runs((size_t)n_items);
+  std::vector<int32_t> qb((size_t)n_items, -1), dbb((size_t)n_items, -1);
+  hipError_t e;
+  hipStream_t s = db->own_stream;
+  if (query_len == 0 || n_items == 0) {
+    for (int32_t t = 0; t < n_items; ++t) ends[(size_t)t] = make_int4(seqs[t], 0, -1, -1);
+  } else {
+    int RR = 8, W2 = 1;
+    pick_intra(db, query_len, 8, &RR, &W2);
+    if ((e = db->q_stage.reserve((size_t)query_len)) != hipSuccess ||
+        (e = db->prof2.reserve((size_t)kIntraCodes * ld)) != hipSuccess)
+      return fail(SW_ENOMEM, std::string("traceback scratch: ") + hipGetErrorString(e));
+    if ((e = hipMemcpyAsync(db->q_stage.p, query, (size_t)query_len, hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+      return hip_fail(e, "query upload");
+    Matrix mat;
+    memcpy(mat.v, matrix, sizeof(mat.v));
+    if ((e = launch_mode_profile(db->q_stage.p, query_len, mat, 16, 0, nullptr, db->prof2.p,
+                                 (int)ld, s)) != hipSuccess)
+      return hip_fail(e, "traceback profile");
+    std::vector<uint8_t> h_dir;
+    int32_t t0 = 0;
+    while (t0 < n_items) {
+      // a group: as many sequences as fit kTraceGroupBytes (at least one)
+      int32_t t1 = t0;
+      int64_t bytes = 0;
+      std::vector<int64_t> off;
+      std::vector<int2> items;
+      while (t1 < n_items) {
+        const int64_t box = (offs[(size_t)seqs[t1] + 1] - offs[(size_t)seqs[t1]]) * ld;
+        if (t1 > t0 && bytes + box > kTraceGroupBytes) break;
+        off.push_back(bytes);
+        items.push_back(make_int2(seqs[t1], 0));
+        bytes += box;
+        ++t1;
+      }
+      const int32_t k = t1 - t0;
+      if ((e = db->trace_dir.reserve((size_t)std::max<int64_t>(bytes, 8))) != hipSuccess ||
+          (e = db->trace_items.reserve((size_t)k)) != hipSuccess ||
+          (e = db->trace_off.reserve((size_t)k)) != hipSuccess ||
+          (e = db->trace_ends.reserve((size_t)k)) != hipSuccess)
+        return fail(SW_ENOMEM, std::string("traceback codes: ") + hipGetErrorString(e));
+      try {
+        h_dir.resize((size_t)bytes);
+      } catch (...) {
+        return fail(SW_ENOMEM, "host allocation failed");
+      }
+      if ((e = hipMemcpyAsync(db->trace_items.p, items.data(), (size_t)k * sizeof(int2),
+                              hipMemcpyHostToDevice, s)) != hipSuccess ||
+          (e = hipMemcpyAsync(db->trace_off.p, off.data(), (size_t)k * sizeof(int64_t),
+                              hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "traceback items");
+      IntraArgs ta{};
+      ta.res = db->d->res.p;
+      ta.offs = db->d->offs.p;
+      ta.items = db->trace_items.p;
+      ta.count_ptr = nullptr;
+      ta.count = k;
+      ta.prof2 = db->prof2.p;
+      ta.q0.prof2_off = 0;
+      ta.q0.out_off = 0;
+      ta.q0.m_pad2 = (int32_t)ld;
+      ta.q0.n_pass = (query_len + 64 * RR - 1) / (64 * RR);
+      ta.queries = nullptr;
+      ta.go = gap_open;
+      ta.ge = gap_extend;
+      ta.scratch = db->rb_resc.p;
+      ta.scratch_stride = rescore_stride(db->d->plan);
+      ta.out = nullptr;
+      ta.ends = db->trace_ends.p;
+      ta.dir = db->trace_dir.p;
+      ta.dir_off = db->trace_off.p;
+      ta.dir_ld = ld;
+      if ((e = launch_intra(RR, W2, std::min<int>(k, kIntraGridRescore), ta, s)) != hipSuccess)
+        return hip_fail(e, "traceback kernel");
+      if ((e = hipMemcpyAsync(ends.data() + t0, db->trace_ends.p, (size_t)k * sizeof(int4),
+                              hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (bytes > 0 && (e = hipMemcpyAsync(h_dir.data(), db->trace_dir.p, (size_t)bytes,
+                                            hipMemcpyDeviceToHost, s)) != hipSuccess) ||
+          (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "traceback download");
+      // the walks, one host thread per sequence of the group
+      std::atomic<int32_t> next{0};
+      std::atomic<bool> bad{false};
+      auto work = [&]() {
+        for (int32_t x; (x = next.fetch_add(1)) < k;) {
+          const int4 en = ends[(size_t)(t0 + x)];
+          if (en.y <= 0) continue;
+          if (!walk_alignment(h_dir.data() + off[(size_t)x], ld, en.z, en.w, &qb[(size_t)(t0 + x)],
+                              &dbb[(size_t)(t0 + x)], &runs[(size_t)(t0 + x)]))
+            bad = true;
+        }
+      };
+      const int nt = std::max(1, std::min<int>(k, (int)std::thread::hardware_concurrency()));
+      std::vector<std::thread> pool;
+      try {
+        for (int x = 1; x < nt; ++x) pool.emplace_back(work);
+      } catch (...) {
+      }
+      work();
+      for (auto& th : pool) th.join();
+      if (bad) return fail(SW_EDEVICE, "traceback codes do not form a path");
+      t0 = t1;
+    }
+  }
+  int64_t total = 0;
+  for (const auto& r : runs) total += (int64_t)r.size();
+  if (ops_used) *ops_used = total;
+  if (total > ops_cap)
+    return fail(SW_ERANGE, "the alignments take " + std::to_string(total) +
+                               " operation runs, more than ops_cap (" + std::to_string(ops_cap) + ")");
+  int64_t at = 0;
+  for (int32_t t = 0; t < n_items; ++t) {
+    const int4 en = ends[(size_t)t];
+    sw_alignment& A = out[t];
+    A.seq = seqs[t];
+    A.score = std::max(en.y, 0);
+    A.query_begin = en.y > 0 ? qb[(size_t)t] : -1;
+    A.query_end = en.y > 0 ? en.z : -1;
+    A.db_begin = en.y > 0 ? dbb[(size_t)t] : -1;
+    A.db_end = en.y > 0 ? en.w : -1;
+    A.ops_offset = at;
+    A.n_ops = (int32_t)runs[(size_t)t].size();
+    A.reserved = 0;
+    if (A.n_ops > 0) memcpy(ops + at, runs[(size_t)t].data(), (size_t)A.n_ops * 4);
+    at += A.n_ops;
+  }
+  set_error("");
+  return SW_OK;
+}
+
 static int impl_search_topk_async(swdb::Searcher* db, const uint8_t* d_query, int32_t query_len,
                                   const int8_t* matrix, int32_t gap_open, int32_t gap_extend,
                                   int32_t k, int32_t* d_out_scores, sw_hit* d_hits,
@@ -2619,6 +2842,13 @@ int sw_search_async_noalloc(sw_db* h, const uint8_t* d_query, int32_t query_len,
   return impl_search_async_noalloc(S_of(h), d_query, query_len, matrix, gap_open, gap_extend,
                                    d_out_scores, hip_stream);
 }
+int sw_traceback(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
+                 int32_t gap_open, int32_t gap_extend, const int32_t* seqs, int32_t n_items,
+                 sw_alignment* out, uint32_t* ops, int64_t ops_cap, int64_t* ops_used) {
+  return impl_traceback(S_of(h), query, query_len, matrix, gap_open, gap_extend, seqs, n_items,
+                        out, ops, ops_cap, ops_used);
+}
+
 int sw_search_topk(sw_db* h, const uint8_t* query, int32_t query_len, const int8_t* matrix,
                    int32_t gap_open, int32_t gap_extend, int32_t k, int32_t* out_scores,
                    sw_hit* out_hits) {
