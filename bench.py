@@ -322,7 +322,8 @@ def hybrid_leg(db, w, host_rt, steps=2):
 def topk_leg(db, w, k=1000, queries=(0, 8, 19)):
     """The top-k hits with alignment ends (sw_search_topk_async) against the
     plain search of the same query: the extra time of the selection and the
-    exact end-coordinate pass over the k hits."""
+    exact end-coordinate pass over the k hits; then the alignments of the 10
+    best (sw_traceback, host call: codes on the device, walks on the host)."""
     import torch
     out = []
     for qi in queries:
@@ -334,8 +335,18 @@ def topk_leg(db, w, k=1000, queries=(0, 8, 19)):
                    for _ in range(3))
         with_k = min(_event_ms(lambda: db.search_topk_async(dq, w.matrix, 10, 2, k, d_out,
                                                             d_hits)) for _ in range(3))
+        torch.cuda.synchronize()
+        best = d_hits[:10, 0].cpu().numpy()
+        tb = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            als = db.traceback(q, w.matrix, 10, 2, best)
+            tb.append((time.perf_counter() - t0) * 1e3)
         out.append({"m": len(q), "k": k, "search_ms": base, "topk_ms": with_k,
-                    "extra_ms": with_k - base})
+                    "extra_ms": with_k - base, "traceback_10_ms": min(tb),
+                    "traceback_10_cells": int(len(q) * sum(int(w.offsets[s + 1] - w.offsets[s])
+                                                         for s in best)),
+                    "traceback_10_ops": int(sum(len(a["ops"]) for a in als))})
     log("top-k: %s" % out)
     return out
 
