@@ -1866,11 +1866,6 @@ static int impl_traceback(swdb::Searcher* db, const uint8_t* query, int32_t quer
           (e = db->trace_off.reserve((size_t)k)) != hipSuccess ||
           (e = db->trace_ends.reserve((size_t)k)) != hipSuccess)
         return fail(SW_ENOMEM, std::string("traceback codes: ") + hipGetErrorString(e));
-      try {
-        h_dir.resize((size_t)bytes);
-      } catch (...) {
-        return fail(SW_ENOMEM, "host allocation failed");
-      }
       if ((e = hipMemcpyAsync(db->trace_items.p, items.data(), (size_t)k * sizeof(int2),
                               hipMemcpyHostToDevice, s)) != hipSuccess ||
           (e = hipMemcpyAsync(db->trace_off.p, off.data(), (size_t)k * sizeof(int64_t),
@@ -1901,10 +1896,32 @@ static int impl_traceback(swdb::Searcher* db, const uint8_t* query, int32_t quer
         return hip_fail(e, "traceback kernel");
       if ((e = hipMemcpyAsync(ends.data() + t0, db->trace_ends.p, (size_t)k * sizeof(int4),
                               hipMemcpyDeviceToHost, s)) != hipSuccess ||
-          (bytes > 0 && (e = hipMemcpyAsync(h_dir.data(), db->trace_dir.p, (size_t)bytes,
-                                            hipMemcpyDeviceToHost, s)) != hipSuccess) ||
           (e = hipStreamSynchronize(s)) != hipSuccess)
         return hip_fail(e, "traceback download");
+      // of each sequence's codes only the columns the walk can visit (up to
+      // the end's), one contiguous copy per sequence (a strided copy to
+      // pageable memory goes column by column and took ~2 ms per sequence)
+      std::vector<int64_t> hld((size_t)k, ld), hoff((size_t)k, 0);
+      int64_t hbytes = 0;
+      for (int32_t x = 0; x < k; ++x) {
+        const int4 en = ends[(size_t)(t0 + x)];
+        hoff[(size_t)x] = hbytes;
+        if (en.y > 0) hbytes += ld * ((int64_t)en.w + 1);
+      }
+      try {
+        h_dir.resize((size_t)std::max<int64_t>(hbytes, 1));
+      } catch (...) {
+        return fail(SW_ENOMEM, "host allocation failed");
+      }
+      for (int32_t x = 0; x < k; ++x) {
+        const int4 en = ends[(size_t)(t0 + x)];
+        if (en.y <= 0) continue;
+        if ((e = hipMemcpyAsync(h_dir.data() + hoff[(size_t)x], db->trace_dir.p + off[(size_t)x],
+                                (size_t)(ld * ((int64_t)en.w + 1)), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess)
+          return hip_fail(e, "traceback download");
+      }
+      if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "traceback download");
       // the walks, one host thread per sequence of the group
       std::atomic<int32_t> next{0};
       std::atomic<bool> bad{false};
@@ -1912,8 +1929,9 @@ static int impl_traceback(swdb::Searcher* db, const uint8_t* query, int32_t quer
         for (int32_t x; (x = next.fetch_add(1)) < k;) {
           const int4 en = ends[(size_t)(t0 + x)];
           if (en.y <= 0) continue;
-          if (!walk_alignment(h_dir.data() + off[(size_t)x], ld, en.z, en.w, &qb[(size_t)(t0 + x)],
-                              &dbb[(size_t)(t0 + x)], &runs[(size_t)(t0 + x)]))
+          if (!walk_alignment(h_dir.data() + hoff[(size_t)x], hld[(size_t)x], en.z, en.w,
+                              &qb[(size_t)(t0 + x)], &dbb[(size_t)(t0 + x)],
+                              &runs[(size_t)(t0 + x)]))
             bad = true;
         }
       };
