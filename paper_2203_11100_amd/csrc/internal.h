@@ -106,6 +106,9 @@ struct IntraArgs {
   int32_t mode;               // SW_MODE_*: local (with or without ends), global,
                               // semi-global (single query q0)
   int32_t m;                  // query length (global and semi-global)
+  const int2* seg_items;      // non-null (ends): items {index into items, segment}
+  int32_t seg_cols;           // over column windows as in IntraPairArgs
+  int32_t seg_overlap;
   uint8_t* dir;               // non-null (with ends): the traceback codes of every
                               // cell, item it's at dir + dir_off[it], column-major
                               // with dir_ld bytes (>= the query's padded rows) per
@@ -240,6 +243,12 @@ hipError_t launch_topk(const int32_t* scores, int64_t n, int32_t k, TopkState* s
                        int32_t* ties, int2* items, hipStream_t s);
 // hits[i] = {items[i].x, 0, -1, -1}: the hit list of an empty query.
 hipError_t launch_empty_hits(const int2* items, int32_t k, int4* hits, hipStream_t s);
+// Column-segment items of k hits (seg0: k + 1 ints, seg_items: cap entries)
+// and the per-hit combination of their ends (k_hits.hip).
+hipError_t launch_hit_segments(const int2* items, int32_t k, const int64_t* offs, int32_t C,
+                               int32_t cap, int32_t* seg0, int2* seg_items, hipStream_t s);
+hipError_t launch_hit_combine(const int2* items, int32_t k, const int32_t* seg0,
+                              const int4* seg_ends, int4* hits, hipStream_t s);
 // Pair profiles for `n_pairs` pairs and intra-task profiles for `n_queries`
 // queries of a batch (see k_misc.hip for the layouts); prof3 (or nullptr)
 // receives the queries' packed long-pair profiles.

@@ -210,6 +210,62 @@ __global__ __launch_bounds__(kSortThreads) void k_topk_sort(const int32_t* __res
   for (int x = t; x < k; x += kSortThreads) items[x] = make_int2(idx[x], 0);
 }
 
+// Column segments of the hit sequences for the end pass of a short query:
+// hit t of length n_t gets max(1, ceil(n_t / C)) items {t, s}, computed over
+// the windows of the long-pair kernel's column segments (each exact in its
+// own columns); seg0[t] is hit t's first item and seg0[k] the total, which
+// the end pass reads on the device.  One workgroup: the counts and their
+// exclusive scan in LDS (k <= SW_MAX_TOPK), then every hit's items.
+__global__ __launch_bounds__(1024) void k_hit_segments(const int2* __restrict__ items, int32_t k,
+                                                       const int64_t* __restrict__ offs, int32_t C,
+                                                       int32_t cap, int32_t* __restrict__ seg0,
+                                                       int2* __restrict__ seg_items) {
+  __shared__ int32_t first[SW_MAX_TOPK + 1];
+  const int t0 = threadIdx.x;
+  for (int t = t0; t < k; t += 1024) {
+    const int sid = items[t].x;
+    const int64_t n = offs[sid + 1] - offs[sid];
+    const int64_t c = (n + C - 1) / C;
+    first[t] = c > 1 ? (int32_t)c : 1;
+  }
+  __syncthreads();
+  if (t0 == 0) {
+    int32_t acc = 0;
+    for (int t = 0; t < k; ++t) {
+      const int32_t c = first[t];
+      first[t] = acc;
+      acc += c;
+    }
+    first[k] = acc < cap ? acc : cap;
+  }
+  __syncthreads();
+  for (int t = t0; t <= k; t += 1024) seg0[t] = first[t];
+  for (int t = t0; t < k; t += 1024) {
+    const int32_t end = t + 1 < k ? first[t + 1] : first[k];
+    for (int32_t x = first[t]; x < end && x < cap; ++x) seg_items[x] = make_int2(t, x - first[t]);
+  }
+}
+
+// Each hit's end from its segments' {sid, score, query end, db end}: the
+// highest score, then the smallest database position, then the smallest
+// query position; (-1, -1) for a score of 0.
+__global__ void k_hit_combine(const int2* __restrict__ items, int32_t k,
+                              const int32_t* __restrict__ seg0, const int4* __restrict__ seg_ends,
+                              int4* __restrict__ hits) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= k) return;
+  int b = 0, bc = INT32_MAX, br = INT32_MAX;
+  for (int32_t x = seg0[t]; x < seg0[t + 1]; ++x) {
+    const int4 e = seg_ends[x];
+    if (e.y > b || (e.y == b && e.y > 0 && (e.w < bc || (e.w == bc && e.z < br)))) {
+      b = e.y;
+      bc = e.w;
+      br = e.z;
+    }
+  }
+  hits[t] = b > 0 ? make_int4(items[t].x, b, br, bc) : make_int4(items[t].x, 0, -1, -1);
+}
+
 __global__ void k_empty_hits(const int2* __restrict__ items, int32_t k, int4* __restrict__ hits) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < k) hits[i] = make_int4(items[i].x, 0, -1, -1);
@@ -233,6 +289,23 @@ hipError_t launch_topk(const int32_t* scores, int64_t n, int32_t k, TopkState* s
   hipLaunchKernelGGL(k_topk_collect, dim3(grid), dim3(kSelThreads), 0, s, scores, n, st, gt, ties);
   hipLaunchKernelGGL(k_topk_sort, dim3(1), dim3(kSortThreads), 0, s, scores, st, gt, ties, k,
                      items);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_segments(const int2* items, int32_t k, const int64_t* offs, int32_t C,
+                               int32_t cap, int32_t* seg0, int2* seg_items, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  if (k > SW_MAX_TOPK || C <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hit_segments, dim3(1), dim3(1024), 0, s, items, k, offs, C, cap, seg0,
+                     seg_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_combine(const int2* items, int32_t k, const int32_t* seg0,
+                              const int4* seg_ends, int4* hits, hipStream_t s) {
+  if (k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hit_combine, dim3((k + 255) / 256), dim3(256), 0, s, items, k, seg0,
+                     seg_ends, hits);
   return hipGetLastError();
 }
 

@@ -166,7 +166,10 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
   const int go = a.go, ge = a.ge;
 
   for (int it = blockIdx.x; it < count; it += gridDim.x) {
-    const int2 item = a.items[it];
+    // kEnds with segments: item {hit, segment}; columns [c0, hi) of the hit
+    // sequence as in the long-pair kernel's column segments
+    const int2 sg = a.seg_items ? a.seg_items[it] : make_int2(it, 0);
+    const int2 item = a.items[sg.x];
     const int sid = item.x;
     const QueryDesc qd = a.queries ? a.queries[item.y] : a.q0;
     const int P = qd.n_pass;
@@ -174,8 +177,16 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
     const int my_rounds = (w < P) ? (P - 1 - w) / W2 + 1 : 0;
     const int8_t* __restrict__ qprof = a.prof2 + qd.prof2_off;
     const int64_t b0 = a.offs[sid];
-    const int n = (int)(a.offs[sid + 1] - b0);
+    int n = (int)(a.offs[sid + 1] - b0);
     const uint8_t* __restrict__ bseq = a.res + b0;
+    int c0 = 0;
+    if (kEnds && a.seg_items) {
+      const int lo = sg.y * a.seg_cols;
+      const int hi = min(n, lo + a.seg_cols);
+      c0 = max(0, lo - a.seg_overlap);
+      n = max(hi - c0, 0);
+      bseq += c0;
+    }
     uint8_t* __restrict__ dir = kTrace ? a.dir + a.dir_off[it] : nullptr;
     // supersteps per pass: n + 63 steps, at least kSkew*W2 (see above)
     const int C2 = max((n + 63 + 63) >> 6, kSkew * W2);
@@ -347,7 +358,7 @@ __global__ __launch_bounds__(64 * W2) void k_intra_i32(IntraArgs a) {
           if (end_before(lbest[x], lpos[2 * x], lpos[2 * x + 1], b, bc, br)) {
             b = lbest[x]; bc = lpos[2 * x]; br = lpos[2 * x + 1];
           }
-        a.ends[it] = b > 0 ? make_int4(sid, b, br, bc) : make_int4(sid, 0, -1, -1);
+        a.ends[it] = b > 0 ? make_int4(sid, b, br, bc + c0) : make_int4(sid, 0, -1, -1);
       }
     } else {
 #pragma unroll

@@ -911,14 +911,28 @@ int enqueue_search_kernels(Searcher* db, const SearchShape& sh, const SearchScra
 // stream s (its intra-task profile is still in db->prof2): device top-k
 // selection, then the exact 32-bit intra-task kernel with end tracking over
 // the k hit sequences, writing {seq, score, query end, db end} to d_hits.
-int enqueue_hits(Searcher* db, int32_t m, int32_t go, int32_t ge, const int32_t* d_scores,
-                 int32_t k, sw_hit* d_hits, hipStream_t s) {
+int enqueue_hits(Searcher* db, int32_t m, const Matrix& mat, int32_t go, int32_t ge,
+                 const int32_t* d_scores, int32_t k, sw_hit* d_hits, hipStream_t s) {
   hipError_t e;
   const int64_t n = db->d->n_seqs;
   k = (int32_t)std::min<int64_t>(k, n);
   if (k <= 0) return SW_OK;
+  // short queries: the hit sequences in column segments (as the long pairs
+  // of the search: windows reaching seg_overlap columns back), so a long hit
+  // no longer sets the end pass's time
+  const int32_t overlap = m > 0 ? seg_overlap(*db->d, m, mat, ge) : -1;
+  const int32_t C = db->d->seg_cols;
+  const int64_t per_hit =
+      overlap >= 0 ? std::max<int64_t>(1, (db->d->plan.max_len + C - 1) / C) : 0;
+  const int32_t cap = (int32_t)std::min<int64_t>((int64_t)k * per_hit, INT32_MAX);
   const size_t st_words = sizeof(TopkState) / 4;
-  if ((e = db->topk.reserve(st_words + 4 * (size_t)k)) != hipSuccess)
+  // state, gt[k], ties[k], items[k] (int2); with segments seg0[k + 1],
+  // seg_items[cap] (int2) and, 16-byte aligned, seg_ends[cap] (int4)
+  const size_t seg0_at = st_words + 4 * (size_t)k;
+  const size_t sitems_at = seg0_at + (((size_t)k + 1 + 1) & ~size_t(1));
+  const size_t sends_at = (sitems_at + 2 * (size_t)cap + 3) & ~size_t(3);
+  const size_t words = overlap >= 0 ? sends_at + 4 * (size_t)cap : seg0_at;
+  if ((e = db->topk.reserve(words)) != hipSuccess)
     return fail(SW_ENOMEM, std::string("top-k scratch: ") + hipGetErrorString(e));
   TopkState* st = reinterpret_cast<TopkState*>(db->topk.p);
   int32_t* gt = db->topk.p + st_words;
@@ -951,6 +965,25 @@ int enqueue_hits(Searcher* db, int32_t m, int32_t go, int32_t ge, const int32_t*
   ea.scratch_stride = rescore_stride(db->d->plan);
   ea.out = nullptr;
   ea.ends = reinterpret_cast<int4*>(d_hits);
+  if (overlap >= 0) {
+    int32_t* seg0 = db->topk.p + seg0_at;
+    int2* seg_items = reinterpret_cast<int2*>(db->topk.p + sitems_at);
+    int4* seg_ends = reinterpret_cast<int4*>(db->topk.p + sends_at);
+    if ((e = launch_hit_segments(items, k, db->d->offs.p, C, cap, seg0, seg_items, s)) !=
+        hipSuccess)
+      return hip_fail(e, "hit segments");
+    ea.seg_items = seg_items;
+    ea.seg_cols = C;
+    ea.seg_overlap = overlap;
+    ea.count_ptr = seg0 + k;
+    ea.ends = seg_ends;
+    if ((e = launch_intra(RR, W2, std::min<int>(cap, kIntraGridRescore), ea, s)) != hipSuccess)
+      return hip_fail(e, "hit-end kernel");
+    if ((e = launch_hit_combine(items, k, seg0, seg_ends, reinterpret_cast<int4*>(d_hits), s)) !=
+        hipSuccess)
+      return hip_fail(e, "hit ends");
+    return SW_OK;
+  }
   const int grid = std::min<int>(k, kIntraGridRescore);
   if ((e = launch_intra(RR, W2, grid, ea, s)) != hipSuccess) return hip_fail(e, "hit-end kernel");
   return SW_OK;
@@ -1990,7 +2023,8 @@ static int impl_search_topk_async(swdb::Searcher* db, const uint8_t* d_query, in
   memcpy(mat.v, matrix, sizeof(mat.v));
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   rc = enqueue_search(db, d_query, query_len, mat, gap_open, gap_extend, d_out_scores, s);
-  if (rc == SW_OK) rc = enqueue_hits(db, query_len, gap_open, gap_extend, d_out_scores, k, d_hits, s);
+  if (rc == SW_OK)
+    rc = enqueue_hits(db, query_len, mat, gap_open, gap_extend, d_out_scores, k, d_hits, s);
   mark_caller_work(db, s);
   if (rc == SW_OK) set_error("");
   return rc;
@@ -2027,7 +2061,7 @@ static int impl_search_topk(swdb::Searcher* db, const uint8_t* query, int32_t qu
   memcpy(mat.v, matrix, sizeof(mat.v));
   rc = enqueue_search(db, db->q_stage.p, query_len, mat, gap_open, gap_extend, db->out_stage.p, s);
   if (rc == SW_OK)
-    rc = enqueue_hits(db, query_len, gap_open, gap_extend, db->out_stage.p, kk,
+    rc = enqueue_hits(db, query_len, mat, gap_open, gap_extend, db->out_stage.p, kk,
                       reinterpret_cast<sw_hit*>(db->hits_stage.p), s);
   if (rc != SW_OK) {
     (void)hipStreamSynchronize(s);

@@ -172,3 +172,34 @@ def test_topk_full_size_plain_workload(sw):
             s, qe, de = ocpu.search_end(q, w.residues, w.offsets, w.matrix, 10, 2, ids=order)
             assert (hits["score"] == s).all()
             assert (hits["query_end"] == qe).all() and (hits["db_end"] == de).all()
+
+
+@pytest.mark.parametrize("m,go,ge", [(1, 10, 2), (12, 10, 2), (60, 10, 2), (150, 10, 2),
+                                     (40, 5, 1), (100, 40, 20)])
+def test_topk_ends_in_column_segments(sw, m, go, ge):
+    """Short queries against long hit sequences: the end pass runs in column
+    segments of 4,096 columns (windows reaching m + ceil(11 m / extend)
+    back).  Copies of the query planted to end exactly at, just before and
+    just after a segment boundary, and two equal copies in different
+    segments of one sequence (the first must be reported): every hit's
+    score and end equal the oracle's."""
+    rng = np.random.default_rng(80 + m + ge)
+    q = swinputs.random_residues(m, rng)
+    lengths = np.concatenate([rng.integers(20, 600, 300),
+                              [4095, 4096, 4097, 8192, 9000, 20000, 12345]]).astype(np.int64)
+    res, offs = swinputs.make_database(lengths, rng)
+    res = res.copy()
+    n = len(lengths)
+    big = {int(L): i for i, L in enumerate(lengths) if L >= 4095}
+    plants = [(big[8192], 4096 - m), (big[9000], 4096 - m + 1), (big[4097], 4097 - m),
+              (big[20000], 5000), (big[20000], 13000), (big[12345], 8191 - m + 1)]
+    for sid, at in plants:
+        if at >= 0:
+            res[offs[sid] + at: offs[sid] + at + m] = q
+    say("segmented ends m=%d gaps %d/%d" % (m, go, ge))
+    with sw.Database(res, offs) as db:
+        hits, scores = db.search_topk(q, B62, go, ge, k=64, scores=True)
+    _check_hits(hits, scores, q, res, offs, B62, go, ge, 64)
+    if m >= 12:   # the planted copies outscore the rest
+        long_hits = [h for h in hits if lengths[h["seq"]] > 4096]
+        assert long_hits, "the hits include sequences longer than one segment"
