@@ -41,8 +41,8 @@ METRIC = "GCUPS on 1 MI355X (plain vs batched/served) + p50/p99 query latency"
 # converted to bytes with the counters' readings for a 1 GiB device copy.
 # Valid only for the kernel and schedule-selection code it was taken on: bench
 # reports null when the digest of that code (comments removed) differs.
-TRAFFIC = {"bytes_per_launch": 2.2660e+10, "fetch_bytes": 57.48e9, "write_bytes": 395.71e9,
-           "launches": 20, "sources_sha256": "84f75f02e9eaadbf5cbd995b9e443046c3c569bd29989fae80478b14b5e5a65d"}
+TRAFFIC = {"bytes_per_launch": 2.2661e+10, "fetch_bytes": 57.47e9, "write_bytes": 395.74e9,
+           "launches": 20, "sources_sha256": "a249759c32e92080bf266af662cbc83bbeded4f712924ea5003a8c8b2876af53"}
 TRAFFIC_SOURCES = ("k_inter.hip", "packed16.h", "internal.h", "runtime.hip")
 # of runtime.hip only the schedule selection (the fitted tables and the
 # choice of rows and waves per query) shapes the inter-task kernel's traffic
