@@ -13,6 +13,8 @@
 #include <vector>
 
 #include <atomic>
+#include <condition_variable>
+#include <memory>
 #include <thread>
 
 #include "cpu_scorer.h"
@@ -196,9 +198,70 @@ struct DbData {
   std::vector<int32_t> h_slots;
 };
 
+// Host threads kept for the hybrid search's CPU share: run(n, f) starts
+// f(0) .. f(n-1) on the first n threads (started on first use), wait()
+// returns when all of them are done.  Starting threads per call had cost
+// tens of microseconds each, per query.
+struct HostPool {
+  std::mutex mu;
+  std::condition_variable cv, done_cv;
+  std::vector<std::thread> threads;
+  std::function<void(int)> job;
+  int64_t gen = 0;
+  int active = 0, running = 0;
+  bool stop = false;
+
+  void loop(int id) {
+    int64_t seen = 0;
+    for (;;) {
+      std::function<void(int)> f;
+      int n = 0;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return stop || gen != seen; });
+        if (stop) return;
+        seen = gen;
+        f = job;
+        n = active;
+      }
+      if (id < n) f(id);
+      std::lock_guard<std::mutex> lk(mu);
+      if (--running == 0) done_cv.notify_all();
+    }
+  }
+  // throws std::system_error if a thread cannot be started
+  void run(int n, std::function<void(int)> f) {
+    while ((int)threads.size() < n) {
+      const int id = (int)threads.size();
+      threads.emplace_back([this, id] { loop(id); });
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      job = std::move(f);
+      active = n;
+      running = (int)threads.size();
+      ++gen;
+    }
+    cv.notify_all();
+  }
+  void wait() {
+    std::unique_lock<std::mutex> lk(mu);
+    done_cv.wait(lk, [&] { return running == 0; });
+  }
+  ~HostPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto& t : threads) t.join();
+  }
+};
+
 // Everything one search mutates: scratch buffers, streams, events, the
 // batch plan, options and counters.  One call at a time per searcher.
 struct Searcher {
+  std::unique_ptr<HostPool> hpool;  // the hybrid search's host threads
   DbData* d = nullptr;
   StreamSet users;                  // streams this searcher's work runs on
   DevBuf<uint4> rb;                 // inter-task boundary rows, all short bins
@@ -293,6 +356,7 @@ void release_searcher(Searcher* db) {
   if (db->own_stream) (void)hipStreamDestroy(db->own_stream);
   if (db->aux_stream) (void)hipStreamDestroy(db->aux_stream);
   db->own_stream = db->aux_stream = nullptr;
+  db->hpool.reset();
 }
 
 void destroy_db(sw_db* h) {
@@ -2164,7 +2228,6 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   std::atomic<bool> gpu_done{false};
   std::atomic<int64_t> cpu_cells{0}, cpu_seqs{0};
   std::atomic<int64_t> cpu_ns{0};
-  std::vector<std::thread> pool;
   // each host thread's {sequence, score} results, applied after the GPU's
   std::vector<std::vector<int2>> host_res((size_t)threads);
   auto worker = [&](int t) {
@@ -2202,10 +2265,17 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
     cpu_seqs += seqs;
     cpu_ns += ns;
   };
+  bool host_started = false;
   try {
-    for (int t = 0; t < threads; ++t) pool.emplace_back(worker, t);
+    if (!db->hpool) db->hpool.reset(new HostPool());
+    db->hpool->run(threads, worker);
+    host_started = true;
   } catch (...) {
-    gpu_done = true;   // no more host work
+    gpu_done = true;   // no host work (threads already started run and end)
+    if (db->hpool && !db->hpool->threads.empty()) {
+      db->hpool->run(0, [](int) {});
+      host_started = true;
+    }
   }
   int64_t gpu_bins = 0;
   auto t_gpu0 = clock::now(), t_gpu1 = t_gpu0;
@@ -2227,7 +2297,7 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
         // nothing left for the GPU: stop the host threads, wait for their
         // current sequences, and look again
         gpu_done = true;
-        for (auto& t : pool) t.join();
+        if (host_started) db->hpool->wait();
         joined = true;
         end = gpu_end();
       }
@@ -2267,8 +2337,7 @@ static int impl_search_hybrid(swdb::Searcher* db, const uint8_t* query, int32_t 
   rc = enqueue_search_kernels(db, sh, X, db->q_stage.p, query_len, mat, gap_open, gap_extend,
                               db->out_stage.p, s, &runner);
   gpu_done = true;
-  if (!joined)
-    for (auto& t : pool) t.join();
+  if (!joined && host_started) db->hpool->wait();
   // the GPU's scores straight into the caller's array, then the host's on
   // top: the GPU scored the bins it took and the long list, a host thread
   // every slot outside the GPU's bins (and perhaps some inside, with the
