@@ -10,8 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswdb.so")
 SOURCES = ["layout.cpp", "runtime.hip", "k_inter.hip", "k_batch.hip", "k_intra.hip", "k_misc.hip", "k_hits.hip", "k_modes.hip",
-           "cpu_scorer.cpp"]
-HOST_SOURCES = ("cpu_scorer.cpp",)
+           "cpu_scorer.cpp", "trace_walk.cpp"]
+HOST_SOURCES = ("cpu_scorer.cpp", "trace_walk.cpp")
 ARCH = os.environ.get("SWDB_OFFLOAD_ARCH", "gfx950")
 
 

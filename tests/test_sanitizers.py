@@ -1,6 +1,7 @@
 """Host code under AddressSanitizer + UndefinedBehaviorSanitizer: the
 database layout (layout.cpp), the hybrid search's host scorer
-(cpu_scorer.cpp) and the C oracle (sw_oracle.c), built with the sanitizers
+(cpu_scorer.cpp), the traceback walk (trace_walk.cpp, over codes the driver
+computes from their definition) and the C oracle (sw_oracle.c), built with the sanitizers
 into one driver (tests/sanitize/driver.cpp) and run on random and edge-case
 inputs.  CPU only."""
 import os
@@ -21,6 +22,7 @@ def test_host_code_under_sanitizers():
         objs = []
         for src, lang in ((os.path.join(csrc, "layout.cpp"), "c++"),
                           (os.path.join(csrc, "cpu_scorer.cpp"), "c++"),
+                          (os.path.join(csrc, "trace_walk.cpp"), "c++"),
                           (os.path.join(ROOT, "oracle", "sw_oracle.c"), "c"),
                           (os.path.join(ROOT, "tests", "sanitize", "driver.cpp"), "c++")):
             obj = os.path.join(tmp, os.path.basename(src) + ".o")
