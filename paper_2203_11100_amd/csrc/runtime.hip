@@ -1079,8 +1079,11 @@ int enqueue_search_mode(Searcher* db, const uint8_t* d_query, int32_t m, const M
       return hip_fail(e, "empty-query kernel");
     return SW_OK;
   }
-  // 16 or 32 rows per strip: the fewer padded rows (32 on a tie)
-  const int R = ((m + 15) / 16 * 16 < (m + 31) / 32 * 32) ? 16 : 32;
+  // 32 rows per strip, 16 for queries of at most 16 residues: each strip
+  // pays its boundary row and profile staging, so taller strips win even
+  // with padding (144 residues: 5 strips of 32 beat 9 of 16; 16-row strips
+  // for every query ran at 1,108 GCUPS against 1,740 with 32)
+  const int R = m <= 16 ? 16 : 32;
   const int n_strips = (m + R - 1) / R;
   const int m_pad2 = intra_rows_pad(m);
   const int64_t short_dwords = P.n_bins < P.n_bins + P.n_long_bins ? P.bins[4 * P.n_bins]
