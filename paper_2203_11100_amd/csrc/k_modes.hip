@@ -84,7 +84,8 @@ __global__ void k_mode_empty_query(const int64_t* __restrict__ offs, int64_t n_s
 
 template <int R, int MODE>
 __global__ __launch_bounds__(256) void k_mode_inter(ModeArgs a) {
-  __shared__ __align__(16) int32_t lprof_all[4][kProfRowDwords * R];
+  constexpr int RS = R + 4;   // LDS stride of a code's row, dwords
+  __shared__ __align__(16) int32_t lprof_all[4][kProfRowDwords * RS];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int hb = blockIdx.x * 4 + w;
@@ -105,7 +106,18 @@ __global__ __launch_bounds__(256) void k_mode_inter(ModeArgs a) {
   for (int s = 0; s < S; ++s) {
     {  // stage the strip's profile (read back only by this wave)
       const int32_t* __restrict__ src = a.prof + (size_t)s * kProfRowDwords * R;
-      for (int x = lane; x < kProfRowDwords * R; x += 64) lprof[x] = src[x];
+      constexpr int N = kProfRowDwords * R, IT = (N + 63) / 64;
+      int32_t v[IT];   // every load in flight before the first write
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int x = it * 64 + lane;
+        v[it] = x < N ? src[x] : 0;
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int x = it * 64 + lane;
+        if (x < N) lprof[(x / R) * RS + x % R] = v[it];
+      }
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
     }
     const bool first = s == 0, last = s == S - 1;
@@ -117,57 +129,69 @@ __global__ __launch_bounds__(256) void k_mode_inter(ModeArgs a) {
       E[k] = H[k] - go;                       // E(i, 1)
     }
     int hdiag = -gapw(row0, go, ge);          // H(row0, 0)
-    // the row above each chunk of 4 columns, loaded one chunk ahead
+    // the row above each chunk of 4 columns, loaded one chunk ahead.  The
+    // loads are issued on every path (the first strip discards them for the
+    // top border) so that no branch around them makes a later wait drain
+    // every outstanding store.
     auto load_up = [&](int j0, int2 (&u)[4], uint32_t& rw) {
       rw = res[(size_t)(j0 >> 2) * 128];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (first) {
-          // the top border H(0, j) and the F it feeds into row 1:
-          // max(F(0, j) - ge, H(0, j) - go) = H(0, j) - go
-          const int top = MODE == SW_MODE_GLOBAL ? -gapw(j0 + q + 1, go, ge) : 0;
-          u[q] = make_int2(top, top - go);
-        } else {
-          u[q] = rb[(size_t)(j0 + q) * 128];
-        }
+        const int2 v = rb[(size_t)(j0 + q) * 128];
+        // the top border H(0, j) and the F it feeds into row 1:
+        // max(F(0, j) - ge, H(0, j) - go) = H(0, j) - go
+        const int top = MODE == SW_MODE_GLOBAL ? -gapw(j0 + q + 1, go, ge) : 0;
+        u[q].x = first ? top : v.x;
+        u[q].y = first ? top - go : v.y;
       }
     };
     int2 up_n[4];
     uint32_t rw_n;
     load_up(0, up_n, rw_n);
+    // the profile column of the next database column is read from LDS one
+    // column ahead, so that its latency hides behind a column of cells
+    int PA[R], PB[R];
+    auto load_prof = [&](uint32_t byte, int (&P)[R]) {
+      const int32_t* pp = lprof + ((byte >> 3) & 31u) * RS;
+#pragma unroll
+      for (int k = 0; k < R; ++k) P[k] = pp[k];
+    };
+    load_prof(rw_n & 0xffu, PA);
     for (int j0 = 0; j0 < L; j0 += 4) {
       int2 up[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) up[q] = up_n[q];
       const uint32_t rw = rw_n;
-      if (j0 + 4 < L) load_up(j0 + 4, up_n, rw_n);
+      load_up(j0 + 4 < L ? j0 + 4 : j0, up_n, rw_n);   // past the end: this chunk again
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = j0 + q;
-        const int32_t* pp = lprof + ((rw >> (8 * q)) & 0xffu) * (R / 8);
+        int (&P)[R] = (q & 1) ? PB : PA;
+        // column j + 1's code: the next byte of this chunk's word, else the
+        // first byte of the next chunk's (this chunk's again past the last)
+        load_prof(q < 3 ? (rw >> (8 * (q + 1))) & 0xffu : rw_n & 0xffu, (q & 1) ? PA : PB);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the cells
         int hd = hdiag;
         hdiag = up[q].x;
         int F = up[q].y;
 #pragma unroll
         for (int k = 0; k < R; ++k) {
-          const int h = imax3(hd + pp[k], E[k], F);
+          const int h = imax3(hd + P[k], E[k], F);
           hd = H[k];
           H[k] = h;
           const int t = h - go;
           E[k] = imax(E[k] - ge, t);
           F = imax(F - ge, t);
         }
-        if (!last) {
-          rb[(size_t)j * 128] = make_int2(H[R - 1], F);
-        } else if (j < n) {
+        // the strip's bottom row for the next one (written in the last strip
+        // too, where nothing reads it: a store on every path)
+        rb[(size_t)j * 128] = make_int2(H[R - 1], F);
+        if (last) {
           int v = H[0];
 #pragma unroll
           for (int k = 1; k < R; ++k) v = k == kstar ? H[k] : v;
-          if (MODE == SW_MODE_GLOBAL) {
-            if (j == n - 1) score = v;
-          } else {
-            score = imax(score, v);
-          }
+          if (MODE == SW_MODE_GLOBAL) score = j == n - 1 ? v : score;
+          else score = j < n ? imax(score, v) : score;
         }
       }
     }
