@@ -635,12 +635,26 @@ int64_t seg_stride(const DbData& d) {
 // started there with a zero border gives exactly the true H in the
 // segment's columns (lower bounds elsewhere).  Used when this reach is at
 // most one segment (short queries) and extend > 0.
-int32_t seg_overlap(const DbData& d, int m, const Matrix& mat, int32_t ge) {
-  if (!d.any_split || ge <= 0) return -1;
+int64_t window_reach(int m, const Matrix& mat, int32_t ge) {
   int max_s = 0;
   for (int x = 0; x < SW_ALPHA * SW_ALPHA; ++x) max_s = std::max<int>(max_s, mat.v[x]);
-  const int64_t reach = (int64_t)m + ((int64_t)m * max_s + ge - 1) / ge;
+  return (int64_t)m + ((int64_t)m * max_s + ge - 1) / ge;
+}
+
+int32_t seg_overlap(const DbData& d, int m, const Matrix& mat, int32_t ge) {
+  if (!d.any_split || ge <= 0) return -1;
+  const int64_t reach = window_reach(m, mat, ge);
   return reach <= d.seg_cols ? (int32_t)reach : -1;
+}
+
+// The same reach for the end pass over top-k hits, whose boundary rows hold
+// a whole sequence: a window may then reach back more than one segment (it
+// starts at column 0 at the latest), and cutting pays whenever a window is
+// shorter than the longest sequence.  -1: whole sequences.
+int32_t hit_overlap(const DbData& d, int m, const Matrix& mat, int32_t ge) {
+  if (ge <= 0) return -1;
+  const int64_t reach = window_reach(m, mat, ge);
+  return (int64_t)d.plan.max_len > (int64_t)d.seg_cols + reach ? (int32_t)reach : -1;
 }
 
 // Schedule of one single-query search: inter-task strips (R rows, W waves),
@@ -982,10 +996,10 @@ int enqueue_hits(Searcher* db, int32_t m, const Matrix& mat, int32_t go, int32_t
   const int64_t n = db->d->n_seqs;
   k = (int32_t)std::min<int64_t>(k, n);
   if (k <= 0) return SW_OK;
-  // short queries: the hit sequences in column segments (as the long pairs
-  // of the search: windows reaching seg_overlap columns back), so a long hit
-  // no longer sets the end pass's time
-  const int32_t overlap = m > 0 ? seg_overlap(*db->d, m, mat, ge) : -1;
+  // the hit sequences in column segments (as the long pairs of the search:
+  // windows reaching the reach of an alignment back), so a long hit no
+  // longer sets the end pass's time
+  const int32_t overlap = m > 0 ? hit_overlap(*db->d, m, mat, ge) : -1;
   const int32_t C = db->d->seg_cols;
   const int64_t per_hit =
       overlap >= 0 ? std::max<int64_t>(1, (db->d->plan.max_len + C - 1) / C) : 0;

@@ -175,14 +175,15 @@ def test_topk_full_size_plain_workload(sw):
 
 
 @pytest.mark.parametrize("m,go,ge", [(1, 10, 2), (12, 10, 2), (60, 10, 2), (150, 10, 2),
-                                     (40, 5, 1), (100, 40, 20)])
+                                     (40, 5, 1), (100, 40, 20), (700, 10, 2), (1500, 10, 2)])
 def test_topk_ends_in_column_segments(sw, m, go, ge):
-    """Short queries against long hit sequences: the end pass runs in column
+    """Queries against long hit sequences: the end pass runs in column
     segments of 4,096 columns (windows reaching m + ceil(11 m / extend)
-    back).  Copies of the query planted to end exactly at, just before and
-    just after a segment boundary, and two equal copies in different
-    segments of one sequence (the first must be reported): every hit's
-    score and end equal the oracle's."""
+    back, more than one segment for the two longest queries, whose early
+    windows then start at column 0).  Copies of the query planted to end
+    exactly at, just before and just after a segment boundary, and two equal
+    copies in different segments of one sequence (the first must be
+    reported): every hit's score and end equal the oracle's."""
     rng = np.random.default_rng(80 + m + ge)
     q = swinputs.random_residues(m, rng)
     lengths = np.concatenate([rng.integers(20, 600, 300),
