@@ -10,14 +10,15 @@ Runs, in one process:
      resident; with --long-only, the plain queries against a database of only
      the plain database's long sequences (2,048 residues or more), so the
      long-sequence kernel runs alone.  --timing adds each search's kernel
-     times (HIP events) to the printed record.
+     times (HIP events) to the printed record.  --mode global or semiglobal
+     runs those alignment modes' searches instead of local ones.
 
 Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`, one counter
 block per run) each dispatch gets its counter value; dividing a search
 kernel's value by the copy kernel's value per MiB converts it into bytes.
 
     python pmc.py [--workload plain|long-mix|plain-small] [--queries 0,19] [--copy-mib 1024]
-                  [--long-only] [--repeat N] [--timing]
+                  [--long-only] [--repeat N] [--timing] [--mode local|global|semiglobal]
 """
 import argparse
 import json
@@ -39,6 +40,7 @@ def main():
     ap.add_argument("--repeat", type=int, default=1)
     ap.add_argument("--workload", default="plain", choices=("plain", "long-mix", "plain-small"))
     ap.add_argument("--timing", action="store_true")
+    ap.add_argument("--mode", default="local", choices=("local", "global", "semiglobal"))
     args = ap.parse_args()
     import numpy as np
     import torch
@@ -68,7 +70,10 @@ def main():
         for _ in range(args.repeat):
             for i in idx:
                 q = torch.from_numpy(w.queries[i]).cuda()
-                db.search_async(q, w.matrix, w.gap_open, w.gap_extend, out)
+                if args.mode == "local":
+                    db.search_async(q, w.matrix, w.gap_open, w.gap_extend, out)
+                else:
+                    db.search_mode_async(q, w.matrix, w.gap_open, w.gap_extend, args.mode, out)
                 torch.cuda.synchronize()
                 st = db.stats()
                 info.append({"query": i, "m": len(w.queries[i]), "inter_cells": st["inter_cells"],
@@ -78,7 +83,7 @@ def main():
                 if args.timing:
                     info[-1].update({k: round(float(st[k]), 3) for k in
                                      ("ms_total", "ms_inter", "ms_intra", "ms_rescore")})
-    print(json.dumps({"copy_mib": args.copy_mib, "workload": args.workload,
+    print(json.dumps({"copy_mib": args.copy_mib, "workload": args.workload, "mode": args.mode,
                       "long_only": args.long_only,
                       "n_seqs": int(len(offs) - 1), "n_residues": int(offs[-1]),
                       "searches": info}), flush=True)
